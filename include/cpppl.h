@@ -1,0 +1,231 @@
+/*
+ * cpppl.h -- C ABI of the MI355X (gfx950) library for the matrix-free CP
+ * decomposition of the CCSD particle-particle-ladder (PPL) tensor.
+ *
+ * What is computed (K. Pierce, "Towards Using Matrix-Free Tensor
+ * Decompositions to Systematically Improve Approximate Tensor-Networks"):
+ *   R_ijab = sum_cd (sum_X B^X_ac B^X_bd) t_ijcd        (eq. dfB, no singles)
+ * is fitted by a rank-R CP model
+ *   CP_ijab = sum_r lambda_r gamma_ir rho_jr alpha_ar beta_br   (eq. cp-ppl)
+ * with alternating least squares (Section "Optimizing the CP-PPL
+ * tensor-network", eq. full_der, the W Gram-Hadamard product and its Cholesky
+ * solve).  R is never formed: each factor's MTTKRP is a chain of contractions
+ * of t and B against the other three factors (eq. distribute, eq. foreachr).
+ *
+ * Conventions for every call:
+ *  - Every call returns a cpppl_status; no C++ exception crosses this ABI.
+ *  - Arrays are row-major, FP64 unless stated.  `on_device` = 0: host pointer;
+ *    non-zero: device pointer on the context's device, ordered on its stream.
+ *  - The caller owns every buffer it passes; inputs are copied into the
+ *    context's workspace before the call returns.
+ *  - Calls that return host values synchronise the context's stream; the
+ *    others only enqueue work.
+ *  - One host thread per context; several contexts may coexist.
+ *  - After CPPPL_E_HIP the context must be destroyed; other errors leave it usable.
+ *  - cpppl_last_error() gives a message for the last failing call on a context.
+ */
+#ifndef CPPPL_H
+#define CPPPL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPPPL_API __attribute__((visibility("default")))
+
+typedef struct cpppl_ctx cpppl_ctx; /* opaque, library-owned */
+typedef struct cpppl_mlp cpppl_mlp; /* opaque, library-owned */
+
+typedef enum {
+  CPPPL_OK = 0,
+  CPPPL_E_ARG = -1,         /* bad argument (null pointer, size, mode) */
+  CPPPL_E_STATE = -2,       /* call out of order (e.g. ALS before inputs) */
+  CPPPL_E_HIP = -3,         /* HIP runtime error; context must be destroyed */
+  CPPPL_E_NOMEM = -4,       /* bound workspace too small / host allocation failed */
+  CPPPL_E_NOT_SPD = -5,     /* normal-equation matrix W not SPD after ridge retries */
+  CPPPL_E_NONFINITE = -6,   /* NaN or Inf in inputs or results */
+  CPPPL_E_UNSUPPORTED = -7  /* operation not available in this configuration */
+} cpppl_status;
+
+/* Operand precision of the MTTKRP contractions.  Grams, W, the Cholesky solve,
+ * the factor masters, the fit and the energy are FP64 in both. */
+typedef enum {
+  CPPPL_FP64 = 0, /* FP64 operands, FP64 accumulation */
+  CPPPL_BF16 = 1  /* bfloat16 operands (t, B, factors, intermediates), FP32 accumulation */
+} cpppl_precision;
+
+typedef struct {
+  int64_t o;    /* occupied orbitals (i, j) */
+  int64_t v;    /* virtual orbitals (a, b, c, d) */
+  int64_t nx;   /* density-fitting auxiliary functions X */
+  int64_t rank; /* CP rank R, 1 <= R <= 4096 */
+} cpppl_dims;
+
+typedef struct {
+  int max_sweeps;        /* number of ALS sweeps (upper bound when a stop rule is set) */
+  int stop_rule;         /* 0: none; 1: |fit_n - fit_{n-1}| < tol (eq. canon);
+                            2: eta < tol (eq. N3_stopping) */
+  double tol;
+  int refine_fp64_sweeps;/* BF16 contexts: FP64 sweeps appended after the BF16 ones */
+  int history_cap;       /* entries available in the report's history arrays */
+  int energy;            /* non-zero: compute E_CP = sum R~ t after the last sweep */
+  int timing;            /* non-zero: time kernel classes with HIP events */
+} cpppl_als_opts;
+
+/* Kernel classes timed when opts.timing is set (index into ms_class / n_class). */
+enum {
+  CPPPL_T_KR_T2 = 0,   /* tau = KR(gamma, rho)^T t   (S2) */
+  CPPPL_T_Y = 1,       /* Y = F^T B                  (S3 / S7 / S8) */
+  CPPPL_T_Z = 2,       /* per-r Y tau                (S4 / S7) */
+  CPPPL_T_M = 3,       /* M = B . Z, split-K         (S5 / S7) */
+  CPPPL_T_G = 4,       /* per-r G = Y_a^T Y_b        (S8) */
+  CPPPL_T_H = 5,       /* H = t . G, split-K         (S9) */
+  CPPPL_T_SOLVE = 6,   /* Grams, W, Cholesky, solve, normalise (S6, S10) */
+  CPPPL_T_FIT = 7,     /* fit, eta, energy scalars (S11, S12) */
+  CPPPL_T_COUNT = 16
+};
+
+typedef struct {
+  int sweeps_done;       /* sweeps run in this call (including refinement) */
+  int ridge_retries;     /* Cholesky retries with a ridge shift */
+  double fit;            /* 1 - ||R - CP|| / ||R||  (eq. cpfit) after the last sweep */
+  double loss;           /* 0.5 ||R - CP||^2 (eq. loss_function) */
+  double inner;          /* <R, CP> */
+  double cp_norm2;       /* ||CP||^2 (eq. cp_norm2) */
+  double eta;            /* ||CP_n - CP_{n-1}|| / ||CP_{n-1}|| of the last sweep */
+  double energy_cp;      /* sum_ijab CP_ijab t_ijab if opts.energy, else NaN */
+  double ms_total;       /* wall time of the sweeps (host clock, stream synchronised) */
+  double ms_class[16];   /* summed kernel-class times (opts.timing) */
+  int n_class[16];       /* kernel launches per class (opts.timing) */
+  double* fit_hist;      /* caller-owned, history_cap entries, or NULL */
+  double* eta_hist;      /* caller-owned, history_cap entries, or NULL */
+  double* ms_hist;       /* caller-owned, per-sweep milliseconds, or NULL */
+} cpppl_als_report;
+
+/* ---- lifecycle ----------------------------------------------------------- */
+
+/* Create a context for `dims` and operand precision `prec` on HIP device
+ * `device`, enqueuing on `hip_stream` (a hipStream_t; NULL = default stream).
+ * The context needs a device workspace before any other call (bind_workspace). */
+CPPPL_API cpppl_status cpppl_create(const cpppl_dims* dims, cpppl_precision prec, int device,
+                                    void* hip_stream, cpppl_ctx** out);
+/* Bytes of device workspace a context with these dims and precision needs. */
+CPPPL_API cpppl_status cpppl_workspace_size(const cpppl_dims* dims, cpppl_precision prec,
+                                            size_t* bytes);
+/* Give the context `bytes` of device memory at `dev_ptr` (256-byte aligned),
+ * owned by the caller and kept alive until cpppl_destroy. E_NOMEM if too small. */
+CPPPL_API cpppl_status cpppl_bind_workspace(cpppl_ctx* ctx, void* dev_ptr, size_t bytes);
+CPPPL_API cpppl_status cpppl_destroy(cpppl_ctx* ctx);
+
+/* ---- inputs --------------------------------------------------------------- */
+
+/* Doubles amplitudes t[i][j][a][b] (o, o, v, v) (tau of eq. B with t1 = 0). */
+CPPPL_API cpppl_status cpppl_load_t2(cpppl_ctx* ctx, const double* t, int on_device);
+/* Virtual-virtual DF block b[X][p][q] (nx, v, v) = D^{pX}_q of eq. SQG.  No
+ * symmetry in (p, q) is assumed. */
+CPPPL_API cpppl_status cpppl_load_df(cpppl_ctx* ctx, const double* b, int on_device);
+/* Replace R by an explicit CP tensor sum_p lam_p fi_ip fj_jp fa_ap fb_bp with
+ * rank_p <= rank columns (fi, fj: o x rank_p; fa, fb: v x rank_p; lam: rank_p
+ * or NULL for ones).  MTTKRPs then use the Gram identity; no energy. */
+CPPPL_API cpppl_status cpppl_load_planted(cpppl_ctx* ctx, const double* fi, const double* fj,
+                                          const double* fa, const double* fb, const double* lam,
+                                          int64_t rank_p, int on_device);
+/* ||R||^2 and E_exact = sum R t, in FP64 (computed once per loaded t and B;
+ * R is streamed in blocks, never stored whole).  energy_exact may be NULL. */
+CPPPL_API cpppl_status cpppl_norm_r2(cpppl_ctx* ctx, double* norm_r2, double* energy_exact);
+
+/* ---- factors: (i, j, a, b) = (gamma o x R, rho o x R, alpha v x R, beta v x R) ---- */
+
+/* lam may be NULL (ones).  Factors need not be normalised. */
+CPPPL_API cpppl_status cpppl_set_factors(cpppl_ctx* ctx, const double* fi, const double* fj,
+                                         const double* fa, const double* fb, const double* lam,
+                                         int on_device);
+/* Any output pointer may be NULL. */
+CPPPL_API cpppl_status cpppl_get_factors(cpppl_ctx* ctx, double* fi, double* fj, double* fa,
+                                         double* fb, double* lam, int on_device);
+
+/* ---- work ---------------------------------------------------------------------- */
+
+/* Run ALS sweeps (order alpha, beta, gamma, rho) from the current factors. */
+CPPPL_API cpppl_status cpppl_als(cpppl_ctx* ctx, const cpppl_als_opts* opts,
+                                 cpppl_als_report* report);
+/* The MTTKRP of one mode (0 i, 1 j, 2 a, 3 b) at the current factors, in
+ * precision `prec` (BF16 needs a BF16 context): m_out is n_mode x R (the
+ * numerator of eq. full_der for that factor, without lambda). */
+CPPPL_API cpppl_status cpppl_mttkrp(cpppl_ctx* ctx, int mode, cpppl_precision prec, double* m_out,
+                                    int on_device);
+/* fit, <R, CP> and ||CP||^2 at the current factors (one FP64 MTTKRP). */
+CPPPL_API cpppl_status cpppl_fit(cpppl_ctx* ctx, double* fit, double* inner, double* cp_norm2);
+/* E_CP = sum_ijab CP_ijab t_ijab at the current factors, FP64. */
+CPPPL_API cpppl_status cpppl_energy(cpppl_ctx* ctx, double* e_cp);
+
+/* ---- learned warm start (previous converged factors -> next warm start) ------------ */
+
+/* Multi-layer perceptron applied per rank column: in_dim -> hidden (x n_hidden,
+ * ReLU) -> out_dim, FP32, weights initialised U(-1/sqrt(fan_in), 1/sqrt(fan_in))
+ * from a counter-based generator keyed by `seed`.  `capacity` = rows of
+ * training pairs it can hold. */
+CPPPL_API cpppl_status cpppl_mlp_create(int in_dim, int hidden, int n_hidden, int out_dim,
+                                        int64_t capacity, uint64_t seed, int device,
+                                        cpppl_mlp** out);
+CPPPL_API cpppl_status cpppl_mlp_destroy(cpppl_mlp* mlp);
+/* Parameters packed in the order W1, b1, W2, b2, ... (W_l: fan_out x fan_in). */
+CPPPL_API cpppl_status cpppl_mlp_num_params(const cpppl_mlp* mlp, int64_t* n);
+CPPPL_API cpppl_status cpppl_mlp_get_params(cpppl_mlp* mlp, float* out, int on_device);
+CPPPL_API cpppl_status cpppl_mlp_set_params(cpppl_mlp* mlp, const float* in, int on_device);
+/* Forward pass on n_rows rows of x (n_rows x in_dim) -> y (n_rows x out_dim). */
+CPPPL_API cpppl_status cpppl_mlp_forward(cpppl_mlp* mlp, const float* x, int64_t n_rows, float* y,
+                                         int on_device);
+/* Loss = mean (y_pred - y)^2 and its gradient (packed like the parameters). */
+CPPPL_API cpppl_status cpppl_mlp_grad(cpppl_mlp* mlp, const float* x, const float* y,
+                                      int64_t n_rows, float* loss, float* grads, int on_device);
+/* Append rows to the training set (x: n x in_dim, y: n x out_dim). */
+CPPPL_API cpppl_status cpppl_mlp_add_rows(cpppl_mlp* mlp, const float* x, const float* y,
+                                          int64_t n_rows, int on_device);
+CPPPL_API cpppl_status cpppl_mlp_clear_rows(cpppl_mlp* mlp);
+/* Adam (lr, 0.9, 0.999, 1e-8) over the stored rows in mini-batches of `batch`
+ * rows (shuffled by a counter-based generator keyed by seed; batch <= 0: full
+ * batch, no shuffle).  loss_hist (host, epochs entries) may be NULL. */
+CPPPL_API cpppl_status cpppl_mlp_train(cpppl_mlp* mlp, int epochs, float lr, int64_t batch,
+                                       uint64_t seed, float* loss_hist);
+CPPPL_API cpppl_status cpppl_mlp_save(cpppl_mlp* mlp, const char* path);
+CPPPL_API cpppl_status cpppl_mlp_load(cpppl_mlp* mlp, const char* path);
+
+/* Warm-start strategies. */
+enum {
+  CPPPL_WS_PLAIN = 0,       /* previous converged factors (the paper's "optimal guess") */
+  CPPPL_WS_LEARNED = 1,     /* previous factors + network correction, judged against PLAIN */
+  CPPPL_WS_FIRST_ORDER = 2  /* previous factors + first-order ALS change from dR (no network) */
+};
+
+/* Feature width of the warm-start network for these dims: 2 (2o + 2v). */
+CPPPL_API int64_t cpppl_ws_in_dim(const cpppl_dims* dims);
+CPPPL_API int64_t cpppl_ws_out_dim(const cpppl_dims* dims);
+
+/* Advance the amplitudes by dt (o, o, v, v) and warm-start the factors.
+ * Computes the matrix-free MTTKRP of dR (the PPL tensor of dt) at the current
+ * (previous converged) factors, forms per-column features [F, dR-MTTKRP W^-1 /
+ * lambda] for the four modes, then sets t <- t + dt and the factors to the
+ * chosen candidate.  For LEARNED, the candidate with the lower
+ * ||CP||^2 - 2 <R, CP> (R of the new t) between the network's and PLAIN is
+ * kept; *chosen reports it (a CPPPL_WS_* value).  The features are kept for
+ * cpppl_ws_training_rows.  mlp may be NULL unless strategy is LEARNED. */
+CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* ctx, const double* dt, int on_device,
+                                        int strategy, cpppl_mlp* mlp, int* chosen);
+/* After ALS from a warm start: write the R training rows of that step (features
+ * of the warm start, and targets = converged minus previous factors, per
+ * column, sign-aligned) into the network's training set. */
+CPPPL_API cpppl_status cpppl_ws_training_rows(cpppl_ctx* ctx, cpppl_mlp* mlp);
+
+/* ---- errors ---------------------------------------------------------------- */
+CPPPL_API const char* cpppl_last_error(const cpppl_ctx* ctx);
+CPPPL_API const char* cpppl_status_str(cpppl_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPPPL_H */

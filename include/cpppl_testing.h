@@ -1,0 +1,37 @@
+/*
+ * cpppl_testing.h -- kernel-level test hooks of libcpppl (not part of the
+ * product ABI; used by the parity tests to check the matrix-core GEMM and the
+ * Cholesky solve in isolation).  All pointers are device pointers on the
+ * current HIP device; work is enqueued on `stream` and the call synchronises it.
+ */
+#ifndef CPPPL_TESTING_H
+#define CPPPL_TESTING_H
+
+#include <stdint.h>
+
+#include "cpppl.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C[b](m,n) = alpha sum_k A[b](m,k) B[b](k,n) + beta C[b](m,n) with
+ * A(m,k) at A + b*sab + m*sam + k*sak, B(k,n) at B + b*sbb + k*sbk + n*sbn,
+ * C(m,n) at C + b*scb + m*scm + n.  in_dtype 0: FP64 operands, 1: BF16
+ * operands (uint16 storage); c_dtype 0: FP64, 1: FP32, 2: BF16.  splits > 1
+ * uses `partial` (splits*batch*M*N doubles). */
+CPPPL_API cpppl_status cpppl_test_gemm(int in_dtype, int64_t M, int64_t N, int64_t K, int64_t batch,
+                                       const void* A, int64_t sam, int64_t sak, int64_t sab,
+                                       const void* B, int64_t sbk, int64_t sbn, int64_t sbb,
+                                       void* C, int64_t scm, int64_t scb, int c_dtype, double alpha,
+                                       double beta, int splits, void* partial, void* stream);
+
+/* W (R x R, SPD, overwritten) -> X (R x n) <- W^{-1} X; status: 0 ok, 1 bad pivot. */
+CPPPL_API cpppl_status cpppl_test_spd_solve(double* W, int64_t R, double* X, int64_t n,
+                                            double* dsave, int* status, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPPPL_TESTING_H */

@@ -1,0 +1,284 @@
+"""Python binding of libcpppl (matrix-free CP-ALS of the CCSD PPL tensor on gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory (the workspace) and the stream.  The
+library must have been built (``python -m paper_2503_10380_amd.build``); if it
+is missing, ``load_library`` raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcpppl.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "cpppl.h")
+
+FP64, BF16 = 0, 1
+PRECISIONS = {"fp64": FP64, "bf16": BF16}
+WS_PLAIN, WS_LEARNED, WS_FIRST_ORDER = 0, 1, 2
+T_CLASSES = ["kr_t2", "y", "z", "m", "g", "h", "solve", "fit"]
+
+STATUS = {0: "ok", -1: "E_ARG", -2: "E_STATE", -3: "E_HIP", -4: "E_NOMEM", -5: "E_NOT_SPD",
+          -6: "E_NONFINITE", -7: "E_UNSUPPORTED"}
+
+
+class CppplError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Dims(C.Structure):
+    _fields_ = [("o", C.c_int64), ("v", C.c_int64), ("nx", C.c_int64), ("rank", C.c_int64)]
+
+
+class AlsOpts(C.Structure):
+    _fields_ = [("max_sweeps", C.c_int), ("stop_rule", C.c_int), ("tol", C.c_double),
+                ("refine_fp64_sweeps", C.c_int), ("history_cap", C.c_int), ("energy", C.c_int),
+                ("timing", C.c_int)]
+
+
+class AlsReport(C.Structure):
+    _fields_ = [("sweeps_done", C.c_int), ("ridge_retries", C.c_int), ("fit", C.c_double),
+                ("loss", C.c_double), ("inner", C.c_double), ("cp_norm2", C.c_double),
+                ("eta", C.c_double), ("energy_cp", C.c_double), ("ms_total", C.c_double),
+                ("ms_class", C.c_double * 16), ("n_class", C.c_int * 16),
+                ("fit_hist", C.POINTER(C.c_double)), ("eta_hist", C.POINTER(C.c_double)),
+                ("ms_hist", C.POINTER(C.c_double))]
+
+
+_lib = None
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+
+
+def header_symbols():
+    """Every function the C header declares."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"CPPPL_API\s+[\w\s\*]+?\b(cpppl_\w+)\s*\(", text)))
+
+
+def load_library(path: str = LIB_PATH):
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2503_10380_amd.build`")
+    # One HIP runtime per process: torch ships its own libamdhip64 (same soname
+    # as ROCm's).  Importing torch first makes the library bind to that copy, so
+    # that torch's streams and device memory are valid handles inside it.
+    import torch  # noqa: F401
+    lib = C.CDLL(path)
+    st = C.c_int
+    sig = {
+        "cpppl_create": (st, [C.POINTER(Dims), C.c_int, C.c_int, _P, C.POINTER(_P)]),
+        "cpppl_workspace_size": (st, [C.POINTER(Dims), C.c_int, C.POINTER(C.c_size_t)]),
+        "cpppl_bind_workspace": (st, [_P, _P, C.c_size_t]),
+        "cpppl_destroy": (st, [_P]),
+        "cpppl_load_t2": (st, [_P, _P, C.c_int]),
+        "cpppl_load_df": (st, [_P, _P, C.c_int]),
+        "cpppl_load_planted": (st, [_P, _P, _P, _P, _P, _P, C.c_int64, C.c_int]),
+        "cpppl_norm_r2": (st, [_P, _D, _D]),
+        "cpppl_set_factors": (st, [_P, _P, _P, _P, _P, _P, C.c_int]),
+        "cpppl_get_factors": (st, [_P, _P, _P, _P, _P, _P, C.c_int]),
+        "cpppl_als": (st, [_P, C.POINTER(AlsOpts), C.POINTER(AlsReport)]),
+        "cpppl_mttkrp": (st, [_P, C.c_int, C.c_int, _P, C.c_int]),
+        "cpppl_fit": (st, [_P, _D, _D, _D]),
+        "cpppl_energy": (st, [_P, _D]),
+        "cpppl_mlp_create": (st, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_uint64, C.c_int,
+                                  C.POINTER(_P)]),
+        "cpppl_mlp_destroy": (st, [_P]),
+        "cpppl_mlp_num_params": (st, [_P, C.POINTER(C.c_int64)]),
+        "cpppl_mlp_get_params": (st, [_P, _P, C.c_int]),
+        "cpppl_mlp_set_params": (st, [_P, _P, C.c_int]),
+        "cpppl_mlp_forward": (st, [_P, _P, C.c_int64, _P, C.c_int]),
+        "cpppl_mlp_grad": (st, [_P, _P, _P, C.c_int64, _P, _P, C.c_int]),
+        "cpppl_mlp_add_rows": (st, [_P, _P, _P, C.c_int64, C.c_int]),
+        "cpppl_mlp_clear_rows": (st, [_P]),
+        "cpppl_mlp_train": (st, [_P, C.c_int, C.c_float, C.c_int64, C.c_uint64, _P]),
+        "cpppl_mlp_save": (st, [_P, C.c_char_p]),
+        "cpppl_mlp_load": (st, [_P, C.c_char_p]),
+        "cpppl_ws_in_dim": (C.c_int64, [C.POINTER(Dims)]),
+        "cpppl_ws_out_dim": (C.c_int64, [C.POINTER(Dims)]),
+        "cpppl_warm_start": (st, [_P, _P, C.c_int, C.c_int, _P, C.POINTER(C.c_int)]),
+        "cpppl_ws_training_rows": (st, [_P, _P]),
+        "cpppl_last_error": (C.c_char_p, [_P]),
+        "cpppl_status_str": (C.c_char_p, [C.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _f64_host(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _ptr_host(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Context:
+    """A CP-PPL problem on one GPU: inputs, factors, ALS sweeps.
+
+    Arrays may be numpy (host) or torch CUDA tensors (device, float64,
+    contiguous); results come back as numpy arrays.
+    """
+
+    def __init__(self, o, v, nx, rank, precision="fp64", device=0, stream=None):
+        torch = _torch()
+        self.lib = load_library()
+        self.dims = Dims(o, v, nx, rank)
+        self.o, self.v, self.nx, self.rank = o, v, nx, rank
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.device = device
+        if stream is None:
+            with torch.cuda.device(device):
+                stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        nbytes = C.c_size_t()
+        self._check(self.lib.cpppl_workspace_size(C.byref(self.dims), self.precision, C.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+        h = _P()
+        self._check(self.lib.cpppl_create(C.byref(self.dims), self.precision, device,
+                                          _P(stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self._call("cpppl_bind_workspace", _P(self._ws.data_ptr()), C.c_size_t(self.workspace_bytes))
+
+    # ------------------------------------------------------------------ plumbing
+    def _check(self, status, h=None):
+        if status != 0:
+            msg = ""
+            if h is not None:
+                m = self.lib.cpppl_last_error(h)
+                msg = m.decode() if m else ""
+            raise CppplError(status, msg)
+
+    def _call(self, name, *args):
+        st = getattr(self.lib, name)(self.h, *args)
+        self._check(st, self.h)
+
+    def _arg(self, x, shape, keep):
+        """(pointer, on_device) for a host or device float64 array of `shape`."""
+        if x is None:
+            return None, 0
+        if hasattr(x, "is_cuda") and x.is_cuda:
+            torch = _torch()
+            if x.dtype != torch.float64 or not x.is_contiguous() or tuple(x.shape) != tuple(shape):
+                raise ValueError(f"device array must be contiguous float64 of shape {shape}")
+            keep.append(x)
+            return _P(x.data_ptr()), 1
+        a = _f64_host(x)
+        if a.shape != tuple(shape):
+            raise ValueError(f"expected shape {shape}, got {a.shape}")
+        keep.append(a)
+        return _ptr_host(a), 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cpppl_destroy(self.h)
+            self.h = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ inputs
+    def load_t2(self, t):
+        keep = []
+        p, dev = self._arg(t, (self.o, self.o, self.v, self.v), keep)
+        self._call("cpppl_load_t2", p, dev)
+
+    def load_df(self, b):
+        keep = []
+        p, dev = self._arg(b, (self.nx, self.v, self.v), keep)
+        self._call("cpppl_load_df", p, dev)
+
+    def load_planted(self, fi, fj, fa, fb, lam=None):
+        rp = np.shape(fi)[1]
+        keep = []
+        ps = [self._arg(x, (n, rp), keep) for x, n in zip((fi, fj, fa, fb),
+                                                        (self.o, self.o, self.v, self.v))]
+        pl, dl = self._arg(lam, (rp,), keep)
+        dev = ps[0][1]
+        self._call("cpppl_load_planted", *[q[0] for q in ps], pl, C.c_int64(rp), dev)
+
+    def norm_r2(self):
+        n2, e = C.c_double(), C.c_double()
+        self._call("cpppl_norm_r2", C.byref(n2), C.byref(e))
+        return n2.value, e.value
+
+    # ------------------------------------------------------------------ factors
+    def set_factors(self, fi, fj, fa, fb, lam=None):
+        keep = []
+        shapes = [(self.o, self.rank), (self.o, self.rank), (self.v, self.rank), (self.v, self.rank)]
+        ps = [self._arg(x, s, keep) for x, s in zip((fi, fj, fa, fb), shapes)]
+        devs = {q[1] for q in ps}
+        if len(devs) != 1:
+            raise ValueError("factors must all be on the host or all on the device")
+        pl, dl = self._arg(lam, (self.rank,), keep)
+        if lam is not None and dl != ps[0][1]:
+            raise ValueError("lam must live where the factors live")
+        self._call("cpppl_set_factors", *[q[0] for q in ps], pl, ps[0][1])
+
+    def get_factors(self):
+        out = [np.empty((n, self.rank)) for n in (self.o, self.o, self.v, self.v)]
+        lam = np.empty(self.rank)
+        self._call("cpppl_get_factors", *[_ptr_host(a) for a in out], _ptr_host(lam), 0)
+        return (*out, lam)
+
+    # ------------------------------------------------------------------ work
+    def als(self, sweeps, stop_rule=0, tol=0.0, refine=0, energy=False, timing=False):
+        cap = sweeps + refine
+        fit = np.full(cap, np.nan)
+        eta = np.full(cap, np.nan)
+        ms = np.full(cap, np.nan)
+        opts = AlsOpts(sweeps, stop_rule, tol, refine, cap, int(bool(energy)), int(bool(timing)))
+        rep = AlsReport()
+        rep.fit_hist = fit.ctypes.data_as(_D)
+        rep.eta_hist = eta.ctypes.data_as(_D)
+        rep.ms_hist = ms.ctypes.data_as(_D)
+        self._call("cpppl_als", C.byref(opts), C.byref(rep))
+        n = rep.sweeps_done
+        return {
+            "sweeps": n, "ridge_retries": rep.ridge_retries, "fit": rep.fit, "loss": rep.loss,
+            "inner": rep.inner, "cp_norm2": rep.cp_norm2, "eta": rep.eta,
+            "energy_cp": rep.energy_cp, "ms_total": rep.ms_total,
+            "ms_class": {k: rep.ms_class[i] for i, k in enumerate(T_CLASSES)},
+            "n_class": {k: rep.n_class[i] for i, k in enumerate(T_CLASSES)},
+            "fit_hist": fit[:n].copy(), "eta_hist": eta[:n].copy(), "ms_hist": ms[:n].copy(),
+        }
+
+    def mttkrp(self, mode, precision=None):
+        prec = self.precision if precision is None else PRECISIONS.get(precision, precision)
+        n = (self.o, self.o, self.v, self.v)[mode]
+        out = np.empty((n, self.rank))
+        self._call("cpppl_mttkrp", mode, prec, _ptr_host(out), 0)
+        return out
+
+    def fit(self):
+        f, i, c = C.c_double(), C.c_double(), C.c_double()
+        self._call("cpppl_fit", C.byref(f), C.byref(i), C.byref(c))
+        return f.value, i.value, c.value
+
+    def energy(self):
+        e = C.c_double()
+        self._call("cpppl_energy", C.byref(e))
+        return e.value

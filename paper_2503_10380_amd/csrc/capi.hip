@@ -1,0 +1,1007 @@
+// C ABI, workspace plan and ALS driver of the CP-PPL library.
+//
+// One sweep updates alpha, beta, gamma, rho in that order.  The MTTKRP of each
+// factor is evaluated matrix-free (eq. distribute / eq. foreachr and the same
+// idea for the occupied factors):
+//   tau[r][c][d] = sum_ij gamma_ir rho_jr t_ijcd                     (shared by a, b)
+//   Y_F[r][X][q] = sum_p F_pr B^X_pq                                  (F = alpha or beta)
+//   alpha: Z[r][X][c] = sum_d Y_beta[r][X][d] tau[r][c][d],  M[r][a] = sum_Xc B^X_ac Z[r][X][c]
+//   beta:  Z[r][X][d] = sum_c Y_alpha[r][X][c] tau[r][c][d], M[r][b] = sum_Xd B^X_bd Z[r][X][d]
+//   G[r][c][d] = sum_X Y_alpha[r][X][c] Y_beta[r][X][d],  H[r][ij] = sum_cd G[r][cd] t_ijcd
+//   gamma: M[r][i] = sum_j H[r][ij] rho_jr;  rho: M[r][j] = sum_i H[r][ij] gamma_ir
+// then F^T = W^{-1} M^T with W the Hadamard product of the other three Grams,
+// Cholesky-factored in FP64, and the rows of F^T are scaled to unit 2-norm
+// (the norms are lambda).  Y_beta of the updated beta is kept for the next
+// sweep's alpha update (caching of intermediates across gradient evaluations).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <stdexcept>
+#include <string>
+
+#include "ctx.h"
+#include "linalg.h"
+#include "ops.h"
+#include "ws.h"
+
+using namespace cpppl;
+
+namespace cpppl {
+
+StatusError::StatusError(cpppl_status s, std::string m) : st(s), msg(std::move(m)) {}
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int MAX_RANK = 4096;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+int64_t nmode(const cpppl_dims& d, int m) { return m < 2 ? d.o : d.v; }
+
+Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
+  Plan p;
+  size_t off = 0;
+  auto add = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(std::max<size_t>(bytes, 8));
+    return o;
+  };
+  const int64_t o = d.o, v = d.v, X = d.nx, R = d.rank;
+  const size_t o2v2 = (size_t)(o * o * v * v), xv2 = (size_t)(X * v * v);
+  const bool lp = prec == CPPPL_BF16;
+  p.t64 = add(o2v2 * 8);
+  p.t64T = add(o2v2 * 8);
+  p.b64 = add(xv2 * 8);
+  p.b64T = add(xv2 * 8);
+  p.b64P = add(xv2 * 8);
+  p.t16 = lp ? add(o2v2 * 2) : 0;
+  p.t16T = lp ? add(o2v2 * 2) : 0;
+  p.b16T = lp ? add(xv2 * 2) : 0;
+  p.b16P = lp ? add(xv2 * 2) : 0;
+  for (int m = 0; m < 4; ++m) {
+    const size_t n = (size_t)nmode(d, m);
+    p.FT[m] = add(n * R * 8);
+    p.FTprev[m] = add(n * R * 8);
+    p.F16T[m] = lp ? add(n * R * 2) : 0;
+    p.gram[m] = add((size_t)R * R * 8);
+    p.cross[m] = add((size_t)R * R * 8);
+    p.FpT[m] = add(n * R * 8);
+    p.wsF[m] = add(n * R * 8);
+    p.wsD[m] = add(n * R * 8);
+  }
+  p.lam = add(R * 8);
+  p.lamprev = add(R * 8);
+  p.lamp = add(R * 8);
+  p.wsLam = add(R * 8);
+  p.Cp = add((size_t)R * R * 8);
+  p.L = add((size_t)R * R * 8);
+  p.Dsave = add((size_t)diag_save_elems(R) * 8);
+  const int64_t nmax = std::max(o, v);
+  p.MT = add((size_t)nmax * R * 8);
+  p.stage = add((size_t)std::max<int64_t>(nmax * R, R * R) * 8);
+  p.wsFeat = add((size_t)R * 2 * (2 * o + 2 * v) * 4);
+  // intermediates, sized for FP64 and shared by the BF16 path
+  const size_t tau_e = (size_t)(R * v * v), y_e = (size_t)(R * X * v);
+  const size_t z_e = (size_t)(R * std::max(X, v) * v);  // Z, and G (R v^2) aliased on it
+  size_t big_e = tau_e + 2 * y_e + z_e;
+  // the one-time ||R||^2 pass reuses this region: t with (c, d) swapped plus
+  // at least one a-block of (ac|bd) and of R
+  big_e = std::max(big_e, o2v2 + (size_t)(v * v * v) + (size_t)(o * o * v) + 64);
+  p.big = add(big_e * 8);
+  p.big_bytes = big_e * 8;
+  p.tau = p.big;
+  p.Ya = p.tau + tau_e * 8;
+  p.Yb = p.Ya + y_e * 8;
+  p.Z = p.Yb + y_e * 8;
+  p.Kt = add((size_t)(R * o * o) * 8);
+  p.HT = add((size_t)(R * o * o) * 8);
+  p.partial_elems = (size_t)std::max({64 * R * v, 16 * R * o * o, 4 * R * R, (int64_t)1 << 16});
+  p.partial = add(p.partial_elems * 8);
+  p.rowbuf = add((size_t)std::max<int64_t>(R, 4096) * 8);
+  p.sums = add(2 * 1024 * 8);
+  p.scal = add(S_COUNT * 8);
+  p.status = add(16 * 4);
+  p.tdc = 0;
+  p.total = off;
+  return p;
+}
+
+void validate_dims(const cpppl_dims* d) {
+  if (!d) throw std::invalid_argument("dims is NULL");
+  if (d->o <= 0 || d->v <= 0 || d->nx <= 0 || d->rank <= 0)
+    throw std::invalid_argument("all dims must be positive");
+  if (d->rank > MAX_RANK) throw std::invalid_argument("rank exceeds 4096");
+  if (d->o > 4096 || d->v > 65536 || d->nx > (1 << 20)) throw std::invalid_argument("dims too large");
+}
+
+void need_ws(cpppl_ctx* c) {
+  if (!c->ws) throw StatusError(CPPPL_E_STATE, "no workspace bound (cpppl_bind_workspace)");
+}
+
+// ------------------------------------------------------------------ timing
+hipEvent_t next_event(cpppl_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    CPPPL_HIP(hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+struct Span {
+  cpppl_ctx* c;
+  int cls;
+  hipEvent_t a = nullptr;
+  Span(cpppl_ctx* c_, int cls_) : c(c_), cls(cls_) {
+    if (c->timing) {
+      a = next_event(c);
+      CPPPL_HIP(hipEventRecord(a, c->stream));
+    }
+  }
+  ~Span() noexcept(false) {
+    if (c->timing && a) {
+      hipEvent_t b = next_event(c);
+      CPPPL_HIP(hipEventRecord(b, c->stream));
+      c->segs.push_back({cls, a, b});
+    }
+  }
+};
+
+// ------------------------------------------------------------------ paths
+Path path_for(cpppl_ctx* c, DType dt) {
+  const Plan& p = c->plan;
+  Path P;
+  P.dt = dt;
+  if (dt == DType::F64) {
+    P.esz = 8;
+    P.T2 = c->at(p.t64);
+    P.T2T = c->at(p.t64T);
+    P.BnT = c->at(p.b64T);
+    P.Bp = c->at(p.b64P);
+    for (int m = 0; m < 4; ++m) P.FTop[m] = c->at(p.FT[m]);
+  } else {
+    if (c->prec != CPPPL_BF16) throw StatusError(CPPPL_E_UNSUPPORTED, "BF16 path needs a BF16 context");
+    P.esz = 2;
+    P.T2 = c->at(p.t16);
+    P.T2T = c->at(p.t16T);
+    P.BnT = c->at(p.b16T);
+    P.Bp = c->at(p.b16P);
+    for (int m = 0; m < 4; ++m) P.FTop[m] = c->at(p.F16T[m]);
+  }
+  return P;
+}
+
+void run_gemm(const Path& P, const Gemm& g, hipStream_t s) {
+  if (P.dt == DType::F64) gemm_f64(g, s);
+  else gemm_bf16(g, s);
+}
+
+int splits_for(cpppl_ctx* c, const Path& P, int64_t M, int64_t N, int64_t K, int64_t batch) {
+  const int64_t tiles = (P.dt == DType::F64 ? gemm_tiles_f64(M, N) : gemm_tiles_bf16(M, N)) * batch;
+  const int64_t bk = P.dt == DType::F64 ? 16 : 64;
+  int s = choose_splits(tiles, K, 1024, 4 * bk, 256);
+  const int64_t cap = (int64_t)(c->plan.partial_elems / (size_t)std::max<int64_t>(1, M * N * batch));
+  if (s > cap) s = (int)std::max<int64_t>(1, cap);
+  return s;
+}
+
+// ------------------------------------------------------------------ chain steps
+// tau[r][cd] = sum_ij Kt[r][ij] t[ij][cd], Kt = KR(gamma, rho)   (path dtype)
+void compute_tau(cpppl_ctx* c, const Path& P) {
+  Span sp(c, CPPPL_T_KR_T2);
+  const int64_t o = c->d.o, v = c->d.v, R = c->d.rank;
+  khatri_rao_t(c->at<double>(c->plan.FT[0]), c->at<double>(c->plan.FT[1]), o, R, c->at(c->plan.Kt),
+               P.dt, c->stream);
+  Gemm g;
+  g.M = R; g.N = v * v; g.K = o * o;
+  g.A = c->at(c->plan.Kt); g.sam = o * o; g.sak = 1;
+  g.B = P.T2T; g.sbn = o * o; g.sbk = 1;
+  g.C = c->at(c->plan.tau); g.scm = v * v; g.ctype = P.dt;
+  run_gemm(P, g, c->stream);
+}
+
+// Y[r][X][q] = sum_p F[r][p] B^X_pq for F = factor `mode` (2 alpha, 3 beta)
+void compute_Y(cpppl_ctx* c, const Path& P, int mode, size_t out) {
+  Span sp(c, CPPPL_T_Y);
+  const int64_t v = c->d.v, X = c->d.nx, R = c->d.rank;
+  Gemm g;
+  g.M = R; g.N = X * v; g.K = v;
+  g.A = P.FTop[mode]; g.sam = v; g.sak = 1;
+  g.B = P.BnT; g.sbn = v; g.sbk = 1;
+  g.C = c->at(out); g.scm = X * v; g.ctype = P.dt;
+  run_gemm(P, g, c->stream);
+}
+
+// Z for mode a (contract d with tau[r][c][d]) or b (contract c).
+void compute_Z(cpppl_ctx* c, const Path& P, int mode) {
+  Span sp(c, CPPPL_T_Z);
+  const int64_t v = c->d.v, X = c->d.nx, R = c->d.rank;
+  Gemm g;
+  g.batch = R; g.M = X; g.N = v; g.K = v;
+  g.A = c->at(mode == 2 ? c->plan.Yb : c->plan.Ya); g.sam = v; g.sak = 1; g.sab = X * v;
+  g.B = c->at(c->plan.tau); g.sbb = v * v;
+  if (mode == 2) { g.sbn = v; g.sbk = 1; } else { g.sbk = v; g.sbn = 1; }
+  g.C = c->at(c->plan.Z); g.scm = v; g.scb = X * v; g.ctype = P.dt;
+  run_gemm(P, g, c->stream);
+}
+
+// M^T[r][p] = sum_{X,q} Z[r][X][q] B^X_pq  -> MT (FP64)
+void compute_M(cpppl_ctx* c, const Path& P) {
+  Span sp(c, CPPPL_T_M);
+  const int64_t v = c->d.v, X = c->d.nx, R = c->d.rank;
+  Gemm g;
+  g.M = R; g.N = v; g.K = X * v;
+  g.A = c->at(c->plan.Z); g.sam = X * v; g.sak = 1;
+  g.B = P.Bp; g.sbn = X * v; g.sbk = 1;
+  g.C = c->at(c->plan.MT); g.scm = v; g.ctype = DType::F64;
+  g.splits = splits_for(c, P, g.M, g.N, g.K, 1);
+  g.partial = c->at(c->plan.partial);
+  run_gemm(P, g, c->stream);
+}
+
+// G[r][c][d] = sum_X Ya[r][X][c] Yb[r][X][d]   (stored in the Z buffer)
+void compute_G(cpppl_ctx* c, const Path& P) {
+  Span sp(c, CPPPL_T_G);
+  const int64_t v = c->d.v, X = c->d.nx, R = c->d.rank;
+  Gemm g;
+  g.batch = R; g.M = v; g.N = v; g.K = X;
+  g.A = c->at(c->plan.Ya); g.sam = 1; g.sak = v; g.sab = X * v;
+  g.B = c->at(c->plan.Yb); g.sbk = v; g.sbn = 1; g.sbb = X * v;
+  g.C = c->at(c->plan.Z); g.scm = v; g.scb = v * v; g.ctype = P.dt;
+  run_gemm(P, g, c->stream);
+}
+
+// H^T[r][ij] = sum_cd G[r][cd] t[ij][cd]  -> HT (FP64)
+void compute_H(cpppl_ctx* c, const Path& P) {
+  Span sp(c, CPPPL_T_H);
+  const int64_t o = c->d.o, v = c->d.v, R = c->d.rank;
+  Gemm g;
+  g.M = R; g.N = o * o; g.K = v * v;
+  g.A = c->at(c->plan.Z); g.sam = v * v; g.sak = 1;
+  g.B = P.T2; g.sbn = v * v; g.sbk = 1;
+  g.C = c->at(c->plan.HT); g.scm = o * o; g.ctype = DType::F64;
+  g.splits = splits_for(c, P, g.M, g.N, g.K, 1);
+  g.partial = c->at(c->plan.partial);
+  run_gemm(P, g, c->stream);
+}
+
+void compute_occ(cpppl_ctx* c, int mode) {
+  Span sp(c, CPPPL_T_H);
+  const int64_t o = c->d.o, R = c->d.rank;
+  const double* other = c->at<double>(c->plan.FT[mode == 0 ? 1 : 0]);
+  occ_reduce(c->at<double>(c->plan.HT), other, c->at<double>(c->plan.MT), o, R, mode == 0 ? 0 : 1,
+             c->stream);
+}
+
+// MTTKRP of a planted CP tensor via cross Grams.
+void planted_mttkrp(cpppl_ctx* c, int mode) {
+  Span sp(c, CPPPL_T_M);
+  const int64_t R = c->d.rank, P = c->rank_p;
+  const Plan& p = c->plan;
+  int ks[3], nk = 0;
+  for (int k = 0; k < 4; ++k)
+    if (k != mode) ks[nk++] = k;
+  for (int q = 0; q < 3; ++q) {
+    const int k = ks[q];
+    const int64_t n = nmode(c->d, k);
+    Gemm g;
+    g.M = R; g.N = P; g.K = n;
+    g.A = c->at(p.FT[k]); g.sam = n; g.sak = 1;
+    g.B = c->at(p.FpT[k]); g.sbn = n; g.sbk = 1;
+    g.C = c->at(p.cross[q]); g.scm = P; g.ctype = DType::F64;
+    gemm_f64(g, c->stream);
+  }
+  hadamard_scale_cols(c->at<double>(p.cross[0]), c->at<double>(p.cross[1]),
+                      c->at<double>(p.cross[2]), c->at<double>(p.lamp), c->at<double>(p.Cp), R, P,
+                      c->stream);
+  const int64_t n = nmode(c->d, mode);
+  Gemm g;
+  g.M = R; g.N = n; g.K = P;
+  g.A = c->at(p.Cp); g.sam = P; g.sak = 1;
+  g.B = c->at(p.FpT[mode]); g.sbk = n; g.sbn = 1;
+  g.C = c->at(p.MT); g.scm = n; g.ctype = DType::F64;
+  gemm_f64(g, c->stream);
+}
+
+// Gram_m = F_m^T F_m (R x R) from FT_m (R x n).
+void compute_gram(cpppl_ctx* c, int m) {
+  const int64_t n = nmode(c->d, m), R = c->d.rank;
+  Gemm g;
+  g.M = R; g.N = R; g.K = n;
+  g.A = c->at(c->plan.FT[m]); g.sam = n; g.sak = 1;
+  g.B = c->at(c->plan.FT[m]); g.sbn = n; g.sbk = 1;
+  g.C = c->at(c->plan.gram[m]); g.scm = R; g.ctype = DType::F64;
+  gemm_f64(g, c->stream);
+}
+
+void refresh_lowp(cpppl_ctx* c, int m) {
+  if (c->prec != CPPPL_BF16) return;
+  const int64_t n = nmode(c->d, m), R = c->d.rank;
+  convert(c->at<double>(c->plan.FT[m]), c->at(c->plan.F16T[m]), DType::BF16, n * R, c->stream);
+}
+
+void copy_d2d(cpppl_ctx* c, size_t dst, size_t src, size_t bytes) {
+  CPPPL_HIP(hipMemcpyAsync(c->at(dst), c->at(src), bytes, hipMemcpyDeviceToDevice, c->stream));
+}
+
+void sync(cpppl_ctx* c) { CPPPL_HIP(hipStreamSynchronize(c->stream)); }
+
+int read_status(cpppl_ctx* c) {
+  CPPPL_HIP(hipMemcpyAsync(c->host_status, c->at(c->plan.status), 16 * sizeof(int),
+                           hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return c->host_status[0];
+}
+
+// F_m <- M W^{-1} with W = *_{k != m} Gram_k, normalise, refresh Gram_m.
+// careful: synchronise and retry with a ridge shift on failure.  Returns retries.
+int solve_mode(cpppl_ctx* c, int m, bool careful) {
+  Span sp(c, CPPPL_T_SOLVE);
+  const int64_t n = nmode(c->d, m), R = c->d.rank;
+  const Plan& p = c->plan;
+  const double* G[3];
+  int q = 0;
+  for (int k = 0; k < 4; ++k)
+    if (k != m) G[q++] = c->at<double>(p.gram[k]);
+  int retries = 0;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    hadamard(G[0], G[1], G[2], c->at<double>(p.L), R * R, c->stream);
+    if (attempt > 0) add_ridge(c->at<double>(p.L), R, 1e-14 * std::pow(100.0, attempt - 1), c->stream);
+    if (careful) zero_ints(c->at<int>(p.status), 1, c->stream);
+    cholesky(c->at<double>(p.L), R, c->at<double>(p.Dsave), c->at<int>(p.status), c->stream);
+    if (!careful) break;
+    if (read_status(c) == 0) break;
+    retries = attempt + 1;
+    if (attempt == 5) throw StatusError(CPPPL_E_NOT_SPD, "W is not positive definite after 5 ridge retries");
+  }
+  copy_d2d(c, p.FT[m], p.MT, (size_t)(n * R) * 8);
+  spd_solve(c->at<double>(p.L), c->at<double>(p.Dsave), R, c->at<double>(p.FT[m]), n, c->stream);
+  row_normalize(c->at<double>(p.FT[m]), R, n, c->at<double>(p.lam), c->stream);
+  compute_gram(c, m);
+  refresh_lowp(c, m);
+  return retries;
+}
+
+// The MTTKRP of `mode` at the current factors into MT (R x n).
+void mttkrp_into_MT(cpppl_ctx* c, const Path& P, int mode) {
+  if (c->planted) {
+    planted_mttkrp(c, mode);
+    return;
+  }
+  if (mode >= 2) {
+    compute_tau(c, P);
+    if (mode == 2) compute_Y(c, P, 3, c->plan.Yb);
+    else compute_Y(c, P, 2, c->plan.Ya);
+    compute_Z(c, P, mode);
+    compute_M(c, P);
+  } else {
+    compute_Y(c, P, 2, c->plan.Ya);
+    compute_Y(c, P, 3, c->plan.Yb);
+    compute_G(c, P);
+    compute_H(c, P);
+    compute_occ(c, mode);
+  }
+  c->ybeta_valid = false;
+}
+
+// eta terms: nn = cp2 (this sweep), np = lam^T (* F_k^T Fprev_k) lamprev, pp = previous cp2.
+void compute_eta(cpppl_ctx* c) {
+  Span sp(c, CPPPL_T_FIT);
+  const int64_t R = c->d.rank;
+  const Plan& p = c->plan;
+  const double* X[4];
+  for (int m = 0; m < 4; ++m) {
+    const int64_t n = nmode(c->d, m);
+    Gemm g;
+    g.M = R; g.N = R; g.K = n;
+    g.A = c->at(p.FT[m]); g.sam = n; g.sak = 1;
+    g.B = c->at(p.FTprev[m]); g.sbn = n; g.sbk = 1;
+    g.C = c->at(p.cross[m]); g.scm = R; g.ctype = DType::F64;
+    gemm_f64(g, c->stream);
+    X[m] = c->at<double>(p.cross[m]);
+  }
+  double* sc = c->at<double>(p.scal);
+  weighted_hadamard_sum(X, c->at<double>(p.lam), c->at<double>(p.lamprev), R,
+                        c->at<double>(p.rowbuf), sc + S_ETA + 1, c->stream);
+  // sc[S_ETA] = nn = cp2 of this sweep, sc[S_ETA+2] = pp = cp2 of the previous state
+  CPPPL_HIP(hipMemcpyAsync(sc + S_ETA, sc + S_FIT + 1, 8, hipMemcpyDeviceToDevice, c->stream));
+  CPPPL_HIP(hipMemcpyAsync(sc + S_ETA + 2, sc + S_CP2_PREV, 8, hipMemcpyDeviceToDevice, c->stream));
+  finish_eta(sc + S_ETA, c->stream);
+  CPPPL_HIP(hipMemcpyAsync(sc + S_CP2_PREV, sc + S_FIT + 1, 8, hipMemcpyDeviceToDevice, c->stream));
+}
+
+void snapshot(cpppl_ctx* c) {
+  const Plan& p = c->plan;
+  const int64_t R = c->d.rank;
+  for (int m = 0; m < 4; ++m) copy_d2d(c, p.FTprev[m], p.FT[m], (size_t)(nmode(c->d, m) * R) * 8);
+  copy_d2d(c, p.lamprev, p.lam, (size_t)R * 8);
+}
+
+void restore_snapshot(cpppl_ctx* c) {
+  const Plan& p = c->plan;
+  const int64_t R = c->d.rank;
+  for (int m = 0; m < 4; ++m) {
+    copy_d2d(c, p.FT[m], p.FTprev[m], (size_t)(nmode(c->d, m) * R) * 8);
+    compute_gram(c, m);
+    refresh_lowp(c, m);
+  }
+  copy_d2d(c, p.lam, p.lamprev, (size_t)R * 8);
+  c->ybeta_valid = false;
+}
+
+// cp2 of the current factors into sc[S_CP2_PREV] (eta reference for the first sweep).
+void cp2_current(cpppl_ctx* c, double* out) {
+  const double* G[4];
+  for (int m = 0; m < 4; ++m) G[m] = c->at<double>(c->plan.gram[m]);
+  weighted_hadamard_sum(G, c->at<double>(c->plan.lam), c->at<double>(c->plan.lam), c->d.rank,
+                        c->at<double>(c->plan.rowbuf), out, c->stream);
+}
+
+// One ALS sweep on path P; returns ridge retries.
+int sweep(cpppl_ctx* c, const Path& P, bool careful) {
+  const Plan& p = c->plan;
+  int retries = 0;
+  if (c->planted) {
+    for (int m : {2, 3, 0, 1}) {
+      planted_mttkrp(c, m);
+      retries += solve_mode(c, m, careful);
+    }
+  } else {
+    compute_tau(c, P);
+    if (!c->ybeta_valid || c->ybeta_dt != P.dt) compute_Y(c, P, 3, p.Yb);
+    compute_Z(c, P, 2);
+    compute_M(c, P);
+    retries += solve_mode(c, 2, careful);
+    compute_Y(c, P, 2, p.Ya);
+    compute_Z(c, P, 3);
+    compute_M(c, P);
+    retries += solve_mode(c, 3, careful);
+    compute_Y(c, P, 3, p.Yb);
+    c->ybeta_valid = true;
+    c->ybeta_dt = P.dt;
+    compute_G(c, P);
+    compute_H(c, P);
+    compute_occ(c, 0);
+    retries += solve_mode(c, 0, careful);
+    compute_occ(c, 1);
+    retries += solve_mode(c, 1, careful);
+  }
+  {
+    Span sp(c, CPPPL_T_FIT);
+    const double* G[4];
+    for (int m = 0; m < 4; ++m) G[m] = c->at<double>(p.gram[m]);
+    fit_scalars(c->at<double>(p.MT), c->at<double>(p.FT[1]), c->d.o, c->at<double>(p.lam), G,
+                c->d.rank, c->at<double>(p.scal) + S_NORM_R2, c->at<double>(p.rowbuf),
+                c->at<double>(p.scal) + S_FIT, c->stream);
+  }
+  compute_eta(c);
+  return retries;
+}
+
+// ||R||^2 and sum R t, FP64, streaming R in a-blocks through the intermediate region.
+void compute_norm_r2(cpppl_ctx* c) {
+  const Plan& p = c->plan;
+  double* sc = c->at<double>(p.scal);
+  if (c->planted) {
+    const int64_t P = c->rank_p;
+    const double* G[4];
+    for (int m = 0; m < 4; ++m) {
+      const int64_t n = nmode(c->d, m);
+      Gemm g;
+      g.M = P; g.N = P; g.K = n;
+      g.A = c->at(p.FpT[m]); g.sam = n; g.sak = 1;
+      g.B = c->at(p.FpT[m]); g.sbn = n; g.sbk = 1;
+      g.C = c->at(p.cross[m]); g.scm = P; g.ctype = DType::F64;
+      gemm_f64(g, c->stream);
+      G[m] = c->at<double>(p.cross[m]);
+    }
+    weighted_hadamard_sum(G, c->at<double>(p.lamp), c->at<double>(p.lamp), P,
+                          c->at<double>(p.rowbuf), sc + S_NORM_R2, c->stream);
+    set_scalar(sc + S_E_EXACT, std::numeric_limits<double>::quiet_NaN(), c->stream);
+    c->norm_valid = true;
+    return;
+  }
+  const int64_t o = c->d.o, v = c->d.v, X = c->d.nx;
+  const int64_t o2 = o * o, v2 = v * v;
+  double* region = c->at<double>(p.big);
+  const int64_t cap = (int64_t)(p.big_bytes / 8);
+  double* tdc = region;                         // t[ij][d][c]
+  transpose_batched(c->at<double>(p.t64), tdc, DType::F64, o2, v, v, c->stream);
+  int64_t ab = (cap - o2 * v2 - 64) / (v * v2 + o2 * v);
+  ab = std::max<int64_t>(1, std::min<int64_t>(ab, v));
+  double* gblk = tdc + o2 * v2;                 // [a][b][d][c] for a in the block
+  double* rblk = gblk + ab * v * v2;            // [ij][a][b]
+  zero_doubles(sc + S_NORM_R2, 2, c->stream);
+  for (int64_t a0 = 0; a0 < v; a0 += ab) {
+    const int64_t nb = std::min(ab, v - a0);
+    Gemm g1;  // g_a[(b,d)][c] = sum_X B[X][(b,d)] B[X][a][c]
+    g1.batch = nb; g1.M = v2; g1.N = v; g1.K = X;
+    g1.A = c->at(p.b64); g1.sam = 1; g1.sak = v2; g1.sab = 0;
+    g1.B = c->at<double>(p.b64) + a0 * v; g1.sbk = v2; g1.sbn = 1; g1.sbb = v;
+    g1.C = gblk; g1.scm = v; g1.scb = v * v2; g1.ctype = DType::F64;
+    gemm_f64(g1, c->stream);
+    Gemm g2;  // R[ij][(a,b)] = sum_(d,c) t[ij][d][c] g[(a,b)][(d,c)]
+    g2.M = o2; g2.N = nb * v; g2.K = v2;
+    g2.A = tdc; g2.sam = v2; g2.sak = 1;
+    g2.B = gblk; g2.sbn = v2; g2.sbk = 1;
+    g2.C = rblk; g2.scm = nb * v; g2.ctype = DType::F64;
+    gemm_f64(g2, c->stream);
+    sumsq_dot_accumulate(rblk, c->at<double>(p.t64) + a0 * v, o2, nb * v, nb * v, v2,
+                         c->at<double>(p.sums), sc + S_NORM_R2, c->stream);
+  }
+  c->norm_valid = true;
+  c->ybeta_valid = false;  // the region holding Y_beta was overwritten
+}
+
+void ensure_norm(cpppl_ctx* c) {
+  if (!c->norm_valid) compute_norm_r2(c);
+}
+
+void compute_energy(cpppl_ctx* c, double* out) {
+  Span sp(c, CPPPL_T_FIT);
+  if (c->planted) {
+    set_scalar(out, std::numeric_limits<double>::quiet_NaN(), c->stream);
+    return;
+  }
+  const Path P = path_for(c, DType::F64);
+  compute_tau(c, P);
+  energy_from_tau(c->at(c->plan.tau), DType::F64, c->at<double>(c->plan.FT[2]),
+                  c->at<double>(c->plan.FT[3]), c->at<double>(c->plan.lam), c->d.rank, c->d.v,
+                  c->at<double>(c->plan.rowbuf), out, c->stream);
+}
+
+void require_inputs(cpppl_ctx* c) {
+  need_ws(c);
+  if (!c->planted && !(c->have_t && c->have_b))
+    throw StatusError(CPPPL_E_STATE, "load t2 and the DF tensor (or a planted tensor) first");
+  if (!c->have_factors) throw StatusError(CPPPL_E_STATE, "set the factors first");
+}
+
+void load_device_or_host(cpppl_ctx* c, void* dst, const void* src, size_t bytes, int on_device) {
+  CPPPL_HIP(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           c->stream));
+  if (!on_device) sync(c);
+}
+
+void check_finite_input(cpppl_ctx* c, const double* x, int64_t n, const char* what) {
+  zero_ints(c->at<int>(c->plan.status) + 1, 1, c->stream);
+  nonfinite_check(x, n, c->at<int>(c->plan.status) + 1, c->stream);
+  CPPPL_HIP(hipMemcpyAsync(c->host_status, c->at(c->plan.status), 16 * sizeof(int),
+                           hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  if (c->host_status[1]) throw StatusError(CPPPL_E_NONFINITE, std::string("non-finite values in ") + what);
+}
+
+// Derive the operand layouts of t from the FP64 master.
+void derive_t(cpppl_ctx* c) {
+  const Plan& p = c->plan;
+  const int64_t o2 = c->d.o * c->d.o, v2 = c->d.v * c->d.v;
+  transpose_batched(c->at<double>(p.t64), c->at(p.t64T), DType::F64, 1, o2, v2, c->stream);
+  if (c->prec == CPPPL_BF16) {
+    convert(c->at<double>(p.t64), c->at(p.t16), DType::BF16, o2 * v2, c->stream);
+    transpose_batched(c->at<double>(p.t64), c->at(p.t16T), DType::BF16, 1, o2, v2, c->stream);
+  }
+}
+
+void init_after_factors(cpppl_ctx* c) {
+  for (int m = 0; m < 4; ++m) {
+    compute_gram(c, m);
+    refresh_lowp(c, m);
+  }
+  cp2_current(c, c->at<double>(c->plan.scal) + S_CP2_PREV);
+  c->have_factors = true;
+  c->ybeta_valid = false;
+}
+
+}  // namespace
+
+// ---- helpers shared with the warm-start code (ws.h) ----
+void ws_mttkrp_into_MT(cpppl_ctx* c, DType dt, int mode) { mttkrp_into_MT(c, path_for(c, dt), mode); }
+void ws_solve_no_update(cpppl_ctx* c, int mode, size_t out_off) {
+  // out = MT W^{-1} with the current Grams (no normalisation, no state change)
+  const int64_t n = nmode(c->d, mode), R = c->d.rank;
+  const Plan& p = c->plan;
+  const double* G[3];
+  int q = 0;
+  for (int k = 0; k < 4; ++k)
+    if (k != mode) G[q++] = c->at<double>(p.gram[k]);
+  hadamard(G[0], G[1], G[2], c->at<double>(p.L), R * R, c->stream);
+  cholesky(c->at<double>(p.L), R, c->at<double>(p.Dsave), c->at<int>(p.status), c->stream);
+  copy_d2d(c, out_off, p.MT, (size_t)(n * R) * 8);
+  spd_solve(c->at<double>(p.L), c->at<double>(p.Dsave), R, c->at<double>(out_off), n, c->stream);
+}
+void ws_init_after_factors(cpppl_ctx* c) { init_after_factors(c); }
+void ws_derive_t(cpppl_ctx* c) {
+  derive_t(c);
+  c->norm_valid = false;
+  c->ybeta_valid = false;
+}
+void ws_ensure_norm(cpppl_ctx* c) { ensure_norm(c); }
+void ws_copy(cpppl_ctx* c, size_t dst, size_t src, size_t bytes) { copy_d2d(c, dst, src, bytes); }
+void ws_sync(cpppl_ctx* c) { sync(c); }
+int64_t ws_nmode(const cpppl_dims& d, int m) { return nmode(d, m); }
+
+}  // namespace cpppl
+
+// =================================================================== C ABI
+#define API_TRY(c)                                                            \
+  if (!(c)) return CPPPL_E_ARG;                                               \
+  if ((c)->hip_failed) {                                                      \
+    (c)->err = "context unusable after a HIP error";                          \
+    return CPPPL_E_HIP;                                                       \
+  }                                                                           \
+  try {                                                                       \
+    CPPPL_HIP(hipSetDevice((c)->device));
+
+#define API_CATCH(c)                                                          \
+  }                                                                           \
+  catch (const cpppl::StatusError& e) {                                       \
+    (c)->err = e.msg;                                                         \
+    return e.st;                                                              \
+  }                                                                           \
+  catch (const cpppl::HipError& e) {                                          \
+    (c)->hip_failed = true;                                                   \
+    (c)->err = std::string(e.where) + ": " + hipGetErrorString(e.err);        \
+    return CPPPL_E_HIP;                                                       \
+  }                                                                           \
+  catch (const std::invalid_argument& e) {                                    \
+    (c)->err = e.what();                                                      \
+    return CPPPL_E_ARG;                                                       \
+  }                                                                           \
+  catch (const std::bad_alloc&) {                                             \
+    (c)->err = "host allocation failed";                                      \
+    return CPPPL_E_NOMEM;                                                     \
+  }                                                                           \
+  catch (const std::exception& e) {                                           \
+    (c)->err = e.what();                                                      \
+    return CPPPL_E_STATE;                                                     \
+  }                                                                           \
+  (c)->err.clear();                                                           \
+  return CPPPL_OK;
+
+extern "C" {
+
+CPPPL_API cpppl_status cpppl_workspace_size(const cpppl_dims* dims, cpppl_precision prec,
+                                            size_t* bytes) {
+  if (!bytes) return CPPPL_E_ARG;
+  try {
+    validate_dims(dims);
+    if (prec != CPPPL_FP64 && prec != CPPPL_BF16) return CPPPL_E_ARG;
+    *bytes = build_plan(*dims, prec).total;
+  } catch (...) {
+    return CPPPL_E_ARG;
+  }
+  return CPPPL_OK;
+}
+
+CPPPL_API cpppl_status cpppl_create(const cpppl_dims* dims, cpppl_precision prec, int device,
+                                    void* hip_stream, cpppl_ctx** out) {
+  if (!out) return CPPPL_E_ARG;
+  *out = nullptr;
+  try {
+    validate_dims(dims);
+  } catch (...) {
+    return CPPPL_E_ARG;
+  }
+  if (prec != CPPPL_FP64 && prec != CPPPL_BF16) return CPPPL_E_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CPPPL_E_HIP;
+  cpppl_ctx* c = new (std::nothrow) cpppl_ctx();
+  if (!c) return CPPPL_E_NOMEM;
+  c->d = *dims;
+  c->prec = prec;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->plan = build_plan(*dims, prec);
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc((void**)&c->host_scal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->host_status, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    if (c->host_scal) (void)hipHostFree(c->host_scal);
+    delete c;
+    return CPPPL_E_HIP;
+  }
+  *out = c;
+  return CPPPL_OK;
+}
+
+CPPPL_API cpppl_status cpppl_bind_workspace(cpppl_ctx* c, void* dev_ptr, size_t bytes) {
+  API_TRY(c)
+  if (!dev_ptr) throw std::invalid_argument("workspace pointer is NULL");
+  if (((uintptr_t)dev_ptr) % ALIGN) throw std::invalid_argument("workspace must be 256-byte aligned");
+  if (bytes < c->plan.total)
+    throw StatusError(CPPPL_E_NOMEM, "workspace too small: need " + std::to_string(c->plan.total) +
+                                         " bytes, got " + std::to_string(bytes));
+  c->ws = (char*)dev_ptr;
+  c->ws_bytes = bytes;
+  c->have_t = c->have_b = c->have_factors = c->planted = false;
+  c->norm_valid = c->ybeta_valid = c->ws_valid = false;
+  zero_ints(c->at<int>(c->plan.status), 16, c->stream);
+  zero_doubles(c->at<double>(c->plan.scal), S_COUNT, c->stream);
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_destroy(cpppl_ctx* c) {
+  if (!c) return CPPPL_E_ARG;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->host_scal) (void)hipHostFree(c->host_scal);
+  if (c->host_status) (void)hipHostFree(c->host_status);
+  delete c;
+  return CPPPL_OK;
+}
+
+CPPPL_API cpppl_status cpppl_load_t2(cpppl_ctx* c, const double* t, int on_device) {
+  API_TRY(c)
+  need_ws(c);
+  if (!t) throw std::invalid_argument("t is NULL");
+  const int64_t n = c->d.o * c->d.o * c->d.v * c->d.v;
+  load_device_or_host(c, c->at(c->plan.t64), t, (size_t)n * 8, on_device);
+  check_finite_input(c, c->at<double>(c->plan.t64), n, "t2");
+  derive_t(c);
+  c->have_t = true;
+  c->planted = false;
+  c->norm_valid = false;
+  c->ybeta_valid = false;
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_load_df(cpppl_ctx* c, const double* b, int on_device) {
+  API_TRY(c)
+  need_ws(c);
+  if (!b) throw std::invalid_argument("b is NULL");
+  const int64_t v = c->d.v, X = c->d.nx, n = X * v * v;
+  const Plan& p = c->plan;
+  load_device_or_host(c, c->at(p.b64), b, (size_t)n * 8, on_device);
+  check_finite_input(c, c->at<double>(p.b64), n, "the DF tensor");
+  transpose_batched(c->at<double>(p.b64), c->at(p.b64T), DType::F64, X, v, v, c->stream);
+  permute_pxq(c->at<double>(p.b64), c->at(p.b64P), DType::F64, X, v, c->stream);
+  if (c->prec == CPPPL_BF16) {
+    transpose_batched(c->at<double>(p.b64), c->at(p.b16T), DType::BF16, X, v, v, c->stream);
+    permute_pxq(c->at<double>(p.b64), c->at(p.b16P), DType::BF16, X, v, c->stream);
+  }
+  c->have_b = true;
+  c->planted = false;
+  c->norm_valid = false;
+  c->ybeta_valid = false;
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_load_planted(cpppl_ctx* c, const double* fi, const double* fj,
+                                          const double* fa, const double* fb, const double* lam,
+                                          int64_t rank_p, int on_device) {
+  API_TRY(c)
+  need_ws(c);
+  if (!fi || !fj || !fa || !fb) throw std::invalid_argument("planted factor is NULL");
+  if (rank_p < 1 || rank_p > c->d.rank) throw std::invalid_argument("planted rank must be in [1, rank]");
+  const Plan& p = c->plan;
+  const double* src[4] = {fi, fj, fa, fb};
+  for (int m = 0; m < 4; ++m) {
+    const int64_t n = nmode(c->d, m);
+    load_device_or_host(c, c->at(p.stage), src[m], (size_t)(n * rank_p) * 8, on_device);
+    transpose_batched(c->at<double>(p.stage), c->at(p.FpT[m]), DType::F64, 1, n, rank_p, c->stream);
+  }
+  if (lam) {
+    load_device_or_host(c, c->at(p.lamp), lam, (size_t)rank_p * 8, on_device);
+  } else {
+    std::vector<double> ones((size_t)rank_p, 1.0);
+    load_device_or_host(c, c->at(p.lamp), ones.data(), (size_t)rank_p * 8, 0);
+  }
+  c->rank_p = rank_p;
+  c->planted = true;
+  c->norm_valid = false;
+  c->ybeta_valid = false;
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_norm_r2(cpppl_ctx* c, double* norm_r2, double* energy_exact) {
+  API_TRY(c)
+  need_ws(c);
+  if (!norm_r2) throw std::invalid_argument("norm_r2 is NULL");
+  if (!c->planted && !(c->have_t && c->have_b)) throw StatusError(CPPPL_E_STATE, "load t2 and B first");
+  ensure_norm(c);
+  CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(c->plan.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  *norm_r2 = c->host_scal[S_NORM_R2];
+  if (energy_exact) *energy_exact = c->host_scal[S_E_EXACT];
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_set_factors(cpppl_ctx* c, const double* fi, const double* fj,
+                                         const double* fa, const double* fb, const double* lam,
+                                         int on_device) {
+  API_TRY(c)
+  need_ws(c);
+  if (!fi || !fj || !fa || !fb) throw std::invalid_argument("factor is NULL");
+  const Plan& p = c->plan;
+  const int64_t R = c->d.rank;
+  const double* src[4] = {fi, fj, fa, fb};
+  for (int m = 0; m < 4; ++m) {
+    const int64_t n = nmode(c->d, m);
+    load_device_or_host(c, c->at(p.stage), src[m], (size_t)(n * R) * 8, on_device);
+    check_finite_input(c, c->at<double>(p.stage), n * R, "a factor");
+    transpose_batched(c->at<double>(p.stage), c->at(p.FT[m]), DType::F64, 1, n, R, c->stream);
+  }
+  if (lam) {
+    load_device_or_host(c, c->at(p.lam), lam, (size_t)R * 8, on_device);
+  } else {
+    std::vector<double> ones((size_t)R, 1.0);
+    load_device_or_host(c, c->at(p.lam), ones.data(), (size_t)R * 8, 0);
+  }
+  init_after_factors(c);
+  c->ws_valid = false;
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_get_factors(cpppl_ctx* c, double* fi, double* fj, double* fa,
+                                         double* fb, double* lam, int on_device) {
+  API_TRY(c)
+  need_ws(c);
+  if (!c->have_factors) throw StatusError(CPPPL_E_STATE, "no factors set");
+  const Plan& p = c->plan;
+  const int64_t R = c->d.rank;
+  double* dst[4] = {fi, fj, fa, fb};
+  for (int m = 0; m < 4; ++m) {
+    if (!dst[m]) continue;
+    const int64_t n = nmode(c->d, m);
+    transpose_batched(c->at<double>(p.FT[m]), c->at(p.stage), DType::F64, 1, R, n, c->stream);
+    CPPPL_HIP(hipMemcpyAsync(dst[m], c->at(p.stage), (size_t)(n * R) * 8,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    if (!on_device) sync(c);
+  }
+  if (lam)
+    CPPPL_HIP(hipMemcpyAsync(lam, c->at(p.lam), (size_t)R * 8,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_mttkrp(cpppl_ctx* c, int mode, cpppl_precision prec, double* m_out,
+                                    int on_device) {
+  API_TRY(c)
+  if (mode < 0 || mode > 3) throw std::invalid_argument("mode must be 0..3");
+  if (!m_out) throw std::invalid_argument("m_out is NULL");
+  require_inputs(c);
+  const DType dt = prec == CPPPL_BF16 ? DType::BF16 : DType::F64;
+  mttkrp_into_MT(c, path_for(c, dt), mode);
+  const int64_t n = nmode(c->d, mode), R = c->d.rank;
+  transpose_batched(c->at<double>(c->plan.MT), c->at(c->plan.stage), DType::F64, 1, R, n, c->stream);
+  CPPPL_HIP(hipMemcpyAsync(m_out, c->at(c->plan.stage), (size_t)(n * R) * 8,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_fit(cpppl_ctx* c, double* fit, double* inner, double* cp_norm2) {
+  API_TRY(c)
+  require_inputs(c);
+  ensure_norm(c);
+  const Plan& p = c->plan;
+  mttkrp_into_MT(c, path_for(c, DType::F64), 1);
+  const double* G[4];
+  for (int m = 0; m < 4; ++m) G[m] = c->at<double>(p.gram[m]);
+  fit_scalars(c->at<double>(p.MT), c->at<double>(p.FT[1]), c->d.o, c->at<double>(p.lam), G, c->d.rank,
+              c->at<double>(p.scal) + S_NORM_R2, c->at<double>(p.rowbuf),
+              c->at<double>(p.scal) + S_JUDGE, c->stream);
+  CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(p.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  if (fit) *fit = c->host_scal[S_JUDGE + 3];
+  if (inner) *inner = c->host_scal[S_JUDGE + 0];
+  if (cp_norm2) *cp_norm2 = c->host_scal[S_JUDGE + 1];
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_energy(cpppl_ctx* c, double* e_cp) {
+  API_TRY(c)
+  if (!e_cp) throw std::invalid_argument("e_cp is NULL");
+  require_inputs(c);
+  if (c->planted) throw StatusError(CPPPL_E_UNSUPPORTED, "no amplitudes for a planted tensor");
+  compute_energy(c, c->at<double>(c->plan.scal) + S_ENERGY);
+  CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(c->plan.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  *e_cp = c->host_scal[S_ENERGY];
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl_als_report* rep) {
+  API_TRY(c)
+  if (!opts || !rep) throw std::invalid_argument("opts/report is NULL");
+  if (opts->max_sweeps < 0 || opts->refine_fp64_sweeps < 0) throw std::invalid_argument("negative sweep count");
+  if (opts->stop_rule < 0 || opts->stop_rule > 2) throw std::invalid_argument("stop_rule must be 0, 1 or 2");
+  require_inputs(c);
+  ensure_norm(c);
+  const Plan& p = c->plan;
+  c->timing = opts->timing != 0;
+  c->ev_used = 0;
+  c->segs.clear();
+  rep->sweeps_done = 0;
+  rep->ridge_retries = 0;
+  rep->energy_cp = std::numeric_limits<double>::quiet_NaN();
+  for (int k = 0; k < 16; ++k) { rep->ms_class[k] = 0.0; rep->n_class[k] = 0; }
+  const DType main_dt = c->prec == CPPPL_BF16 ? DType::BF16 : DType::F64;
+  const int total = opts->max_sweeps + (c->prec == CPPPL_BF16 ? opts->refine_fp64_sweeps : 0);
+  double prev_fit = std::numeric_limits<double>::quiet_NaN();
+  auto t_start = std::chrono::steady_clock::now();
+  sync(c);
+  t_start = std::chrono::steady_clock::now();
+  bool stop_main = false;
+  for (int s = 0; s < total; ++s) {
+    const bool refining = s >= opts->max_sweeps;
+    if (!refining && stop_main) continue;
+    const Path P = path_for(c, refining ? DType::F64 : main_dt);
+    auto ts = std::chrono::steady_clock::now();
+    snapshot(c);
+    zero_ints(c->at<int>(p.status), 1, c->stream);
+    int retries = sweep(c, P, false);
+    CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(p.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
+    CPPPL_HIP(hipMemcpyAsync(c->host_status, c->at(p.status), 16 * sizeof(int), hipMemcpyDeviceToHost,
+                             c->stream));
+    sync(c);
+    if (c->host_status[0]) {  // a Cholesky pivot failed: redo this sweep with ridge retries
+      restore_snapshot(c);
+      CPPPL_HIP(hipMemcpyAsync(c->at<double>(p.scal) + S_CP2_PREV, &c->host_scal[S_ETA + 2], 8,
+                               hipMemcpyHostToDevice, c->stream));
+      retries = sweep(c, P, true);
+      CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(p.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
+      sync(c);
+    }
+    rep->ridge_retries += retries;
+    const double fit = c->host_scal[S_FIT + 3];
+    const double eta = c->host_scal[S_ETA + 3];
+    if (!std::isfinite(fit) || !std::isfinite(c->host_scal[S_FIT + 1]))
+      throw StatusError(CPPPL_E_NONFINITE, "non-finite fit after sweep " + std::to_string(s + 1));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ts).count();
+    if (rep->fit_hist && rep->sweeps_done < opts->history_cap) rep->fit_hist[rep->sweeps_done] = fit;
+    if (rep->eta_hist && rep->sweeps_done < opts->history_cap) rep->eta_hist[rep->sweeps_done] = eta;
+    if (rep->ms_hist && rep->sweeps_done < opts->history_cap) rep->ms_hist[rep->sweeps_done] = ms;
+    rep->sweeps_done++;
+    rep->fit = fit;
+    rep->eta = eta;
+    rep->inner = c->host_scal[S_FIT + 0];
+    rep->cp_norm2 = c->host_scal[S_FIT + 1];
+    rep->loss = c->host_scal[S_FIT + 4];
+    if (!refining) {
+      if (opts->stop_rule == 1 && std::isfinite(prev_fit) && std::fabs(fit - prev_fit) < opts->tol) stop_main = true;
+      if (opts->stop_rule == 2 && eta < opts->tol) stop_main = true;
+    }
+    prev_fit = fit;
+  }
+  if (opts->energy) {
+    compute_energy(c, c->at<double>(p.scal) + S_ENERGY);
+    CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(p.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  sync(c);
+  rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  if (opts->energy) rep->energy_cp = c->host_scal[S_ENERGY];
+  if (c->timing) {
+    for (auto& sg : c->segs) {
+      float ms = 0.f;
+      CPPPL_HIP(hipEventElapsedTime(&ms, sg.a, sg.b));
+      rep->ms_class[sg.cls] += ms;
+      rep->n_class[sg.cls] += 1;
+    }
+    c->segs.clear();
+    c->timing = false;
+  }
+  API_CATCH(c)
+}
+
+CPPPL_API const char* cpppl_last_error(const cpppl_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+CPPPL_API const char* cpppl_status_str(cpppl_status s) {
+  switch (s) {
+    case CPPPL_OK: return "ok";
+    case CPPPL_E_ARG: return "invalid argument";
+    case CPPPL_E_STATE: return "invalid state";
+    case CPPPL_E_HIP: return "HIP error";
+    case CPPPL_E_NOMEM: return "out of memory";
+    case CPPPL_E_NOT_SPD: return "normal equations not positive definite";
+    case CPPPL_E_NONFINITE: return "non-finite values";
+    case CPPPL_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

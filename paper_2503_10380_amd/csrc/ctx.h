@@ -1,0 +1,88 @@
+// Internal state of a CP-PPL context (not part of the C ABI).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/cpppl.h"
+#include "common.h"
+#include "gemm.h"
+
+namespace cpppl {
+
+// Offsets of every device buffer inside the caller-bound workspace.
+struct Plan {
+  size_t total = 0;
+  // inputs, FP64 masters and layouts
+  size_t t64, t64T, tdc, b64, b64T, b64P;
+  // bfloat16 operand copies (BF16 contexts)
+  size_t t16, t16T, b16T, b16P;
+  // factors (transposed, R x n), weights, snapshots, Grams
+  size_t FT[4], FTprev[4], F16T[4], lam, lamprev;
+  size_t gram[4], cross[4], L, Dsave, MT, stage;
+  // intermediates: one region [tau | Ya | Yb | Z]; G aliases Z
+  size_t big, tau, Ya, Yb, Z;
+  size_t big_bytes;
+  size_t Kt, HT, partial, partial_elems;
+  size_t rowbuf, sums, scal, status;
+  // planted CP tensor
+  size_t FpT[4], lamp, Cp;
+  // warm start
+  size_t wsF[4], wsLam, wsFeat, wsD[4];
+};
+
+enum Scal {  // slots of the device scalar block
+  S_NORM_R2 = 0,
+  S_E_EXACT = 1,
+  S_FIT = 8,     // 8..12: inner, cp2, res2, fit, loss
+  S_ETA = 16,    // 16..19: nn, np, pp, eta
+  S_ENERGY = 20,
+  S_CP2_PREV = 21,
+  S_JUDGE = 24,  // 24..28 judge fit scalars
+  S_COUNT = 64
+};
+
+struct Path {
+  DType dt;
+  size_t esz;
+  const void* T2;   // t[ij][cd]   (o^2 x v^2)
+  const void* T2T;  // t[cd][ij]   (v^2 x o^2)
+  const void* BnT;  // B[X][q][p]  = B^X_pq
+  const void* Bp;   // B[p][X][q]  = B^X_pq
+  const void* FTop[4];
+};
+
+}  // namespace cpppl
+
+struct cpppl_ctx {
+  cpppl_dims d{};
+  cpppl_precision prec = CPPPL_FP64;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool hip_failed = false;
+
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  cpppl::Plan plan;
+
+  bool have_t = false, have_b = false, have_factors = false, planted = false;
+  int64_t rank_p = 0;
+  bool norm_valid = false;
+  bool ybeta_valid = false;
+  cpppl::DType ybeta_dt = cpppl::DType::F64;
+  bool ws_valid = false;      // warm-start snapshot (wsF) holds the factors before the last warm start
+
+  double* host_scal = nullptr;  // pinned, S_COUNT doubles
+  int* host_status = nullptr;   // pinned, 16 ints
+
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Seg { int cls; hipEvent_t a, b; };
+  std::vector<Seg> segs;
+
+  template <typename T = void>
+  T* at(size_t off) { return (T*)(ws + off); }
+};

@@ -1,0 +1,45 @@
+// Strided, batched, split-K matrix-core GEMM for gfx950.
+//
+//   C[b](m, n) = alpha * sum_k A[b](m, k) * B[b](k, n) + beta * C[b](m, n)
+//
+// A(m, k) lives at A + b*sab + m*sam + k*sak and B(k, n) at B + b*sbb + k*sbk + n*sbn;
+// for each operand one of its two strides must be 1 (the contiguous index may
+// be either the contracted one or the free one).  C(m, n) lives at
+// C + b*scb + m*scm + n.  With splits > 1 the K range is cut into `splits`
+// chunks whose partial products go to `partial` (splits*batch*M*N accumulator
+// elements) and are then summed in a fixed order (deterministic).
+#pragma once
+
+#include "common.h"
+
+namespace cpppl {
+
+enum class DType : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+struct Gemm {
+  int64_t M = 0, N = 0, K = 0, batch = 1;
+  const void* A = nullptr;
+  int64_t sam = 0, sak = 0, sab = 0;
+  const void* B = nullptr;
+  int64_t sbk = 0, sbn = 0, sbb = 0;
+  void* C = nullptr;
+  int64_t scm = 0, scb = 0;
+  DType ctype = DType::F64;
+  double alpha = 1.0, beta = 0.0;
+  int splits = 1;
+  void* partial = nullptr;
+};
+
+// A and B in FP64, accumulation in FP64 (v_mfma_f64_16x16x4f64).
+void gemm_f64(const Gemm& g, hipStream_t s);
+// A and B in bfloat16, accumulation in FP32 (v_mfma_f32_16x16x32_bf16); beta must be 0.
+void gemm_bf16(const Gemm& g, hipStream_t s);
+
+// Split count giving roughly `target_blocks` work-groups, with at least
+// `min_k` of K per split.
+int choose_splits(int64_t tiles, int64_t K, int64_t target_blocks, int64_t min_k, int max_splits);
+
+int64_t gemm_tiles_f64(int64_t M, int64_t N);
+int64_t gemm_tiles_bf16(int64_t M, int64_t N);
+
+}  // namespace cpppl

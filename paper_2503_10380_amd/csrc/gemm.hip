@@ -1,0 +1,466 @@
+// Matrix-core GEMM kernels for gfx950 (FP64 and BF16 with FP32 accumulation).
+//
+// One work-group of 256 lanes (4 wave64s in a 2 x 2 arrangement) computes a
+// BM x BN tile of C.  K is walked in BK slices staged through LDS with two
+// buffers: the next slice is fetched into registers while the matrix cores
+// work on the current one, so each slice costs a single barrier.
+//
+// LDS layouts are chosen for the fragment reads of each instruction:
+//  * v_mfma_f64_16x16x4f64: lane l needs A(l%16, l/16) and B(l/16, l%16), one
+//    double each, so tiles are kept k-major (As[k][m], Bs[k][n]); its result
+//    element (i, j) is register i/4 of lane j + 16 (i%4);
+//  * v_mfma_f32_16x16x32_bf16: lane l needs 8 consecutive k of row l%16, so
+//    tiles are kept m-major / n-major with 8 bf16 of padding per row
+//    (As[m][k], Bs[n][k]; the padded 144-byte rows make the 16-byte reads of
+//    16 lanes fall on 64 distinct banks); its result element (i, j) is
+//    register i%4 of lane j + 16 (i/4).
+// An operand whose contiguous index is not the one the LDS layout wants is
+// transposed on its way from registers into LDS; global reads stay coalesced.
+// Work-group ids are remapped so that each XCD owns a contiguous range of
+// tiles, and inside a batch the tile dimension with fewer tiles runs fastest,
+// so the larger operand is streamed from HBM about once.
+#include "gemm.h"
+
+#include <algorithm>
+#include <stdexcept>
+
+namespace cpppl {
+
+namespace {
+
+struct KArgs {
+  int64_t M, N, K, batch;
+  const void* A;
+  int64_t sam, sak, sab;
+  const void* B;
+  int64_t sbk, sbn, sbb;
+  void* C;
+  int64_t scm, scb;
+  double alpha, beta;
+  int splits;
+  int64_t kchunk;
+  void* partial;
+  int64_t tiles_m, tiles_n;
+  int vec_ok;
+};
+
+__device__ inline void tile_coords(int64_t lid, const KArgs& a, int64_t& b, int& split,
+                                   int64_t& tm, int64_t& tn) {
+  const int64_t tiles = a.tiles_m * a.tiles_n;
+  const int64_t t = lid % tiles;
+  const int64_t bs = lid / tiles;
+  split = (int)(bs % a.splits);
+  b = bs / a.splits;
+  if (a.tiles_m <= a.tiles_n) {
+    tm = t % a.tiles_m;
+    tn = t / a.tiles_m;
+  } else {
+    tn = t % a.tiles_n;
+    tm = t / a.tiles_n;
+  }
+}
+
+template <typename OutT>
+__device__ inline void store_out(const KArgs& a, int64_t b, int split, int64_t gm, int64_t gn,
+                                 double v) {
+  if (a.splits > 1) {
+    if constexpr (sizeof(OutT) == 8) {
+      ((double*)a.partial)[((int64_t)split * a.batch + b) * a.M * a.N + gm * a.N + gn] = v;
+    } else {
+      ((float*)a.partial)[((int64_t)split * a.batch + b) * a.M * a.N + gm * a.N + gn] = (float)v;
+    }
+    return;
+  }
+  OutT* c = (OutT*)a.C + b * a.scb + gm * a.scm + gn;
+  double r = a.alpha * v;
+  if (a.beta != 0.0) r += a.beta * Conv<OutT>::to_f64(*c);
+  *c = Conv<OutT>::from_f64(r);
+}
+
+// ------------------------------------------------------------------ FP64 ----
+template <int BM, int BN, bool AK, bool BKC>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs a) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  __shared__ double As[2][BK][BM + 1];
+  __shared__ double Bs[2][BK][BN + 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  int64_t b, tm, tn;
+  int split;
+  tile_coords(lid, a, b, split, tm, tn);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int64_t kbeg = (int64_t)split * a.kchunk;
+  const int64_t kend = min(a.K, kbeg + a.kchunk);
+  const double* A = (const double*)a.A + b * a.sab;
+  const double* B = (const double*)a.B + b * a.sbb;
+
+  double ra[EA], rb[EB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * 256;
+      const int mm = AK ? idx / BK : idx % BM;
+      const int kk = AK ? idx % BK : idx / BM;
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      ra[e] = (gm < a.M && gk < kend) ? A[AK ? (gm * a.sam + gk) : (gm + gk * a.sak)] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      const int nn = BKC ? idx / BK : idx % BN;
+      const int kk = BKC ? idx % BK : idx / BN;
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      rb[e] = (gn < a.N && gk < kend) ? B[BKC ? (gn * a.sbn + gk) : (gn + gk * a.sbk)] : 0.0;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * 256;
+      const int mm = AK ? idx / BK : idx % BM;
+      const int kk = AK ? idx % BK : idx / BM;
+      As[buf][kk][mm] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      const int nn = BKC ? idx / BK : idx % BN;
+      const int kk = BKC ? idx % BK : idx / BN;
+      Bs[buf][kk][nn] = rb[e];
+    }
+  };
+
+  d4_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = As[cur][ks + (lane >> 4)][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[j] = Bs[cur][ks + (lane >> 4)][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // v_mfma_f64_16x16x4f64 result layout: element (i, j) of the 16 x 16 tile is
+  // register i / 4 of lane j + 16 * (i % 4).
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * WM + i * 16 + 4 * r + (lane >> 4);
+        const int64_t gn = n0 + wn * WN + j * 16 + (lane & 15);
+        if (gm < a.M && gn < a.N) store_out<double>(a, b, split, gm, gn, acc[i][j][r]);
+      }
+}
+
+// ------------------------------------------------------------------ BF16 ----
+union Pack8 {
+  uint4 u;
+  bf16_t h[8];
+};
+
+template <int BM, int BN, bool AK, bool BKC, typename OutT>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(KArgs a) {
+  constexpr int BK = 64, LDK = BK + 8;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int CA = BM * BK / 8 / 256, CB = BN * BK / 8 / 256;
+  __shared__ __attribute__((aligned(16))) bf16_t As[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN * LDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  int64_t b, tm, tn;
+  int split;
+  tile_coords(lid, a, b, split, tm, tn);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int64_t kbeg = (int64_t)split * a.kchunk;
+  const int64_t kend = min(a.K, kbeg + a.kchunk);
+  const bf16_t* A = (const bf16_t*)a.A + b * a.sab;
+  const bf16_t* B = (const bf16_t*)a.B + b * a.sbb;
+  const bool vec = a.vec_ok != 0;
+
+  Pack8 ra[CA], rb[CB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < CA; ++e) {
+      const int c = tid + e * 256;
+      if (AK) {
+        const int mm = c / (BK / 8), kk = (c % (BK / 8)) * 8;
+        const int64_t gm = m0 + mm, gk = k0 + kk;
+        if (vec && gm < a.M && gk + 8 <= kend) {
+          ra[e].u = *(const uint4*)(A + gm * a.sam + gk);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            ra[e].h[i] = (gm < a.M && gk + i < kend) ? A[gm * a.sam + gk + i] : (bf16_t)0;
+        }
+      } else {
+        const int kk = c / (BM / 8), mm = (c % (BM / 8)) * 8;
+        const int64_t gm = m0 + mm, gk = k0 + kk;
+        if (vec && gk < kend && gm + 8 <= a.M) {
+          ra[e].u = *(const uint4*)(A + gk * a.sak + gm);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            ra[e].h[i] = (gk < kend && gm + i < a.M) ? A[gk * a.sak + gm + i] : (bf16_t)0;
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+      const int c = tid + e * 256;
+      if (BKC) {
+        const int nn = c / (BK / 8), kk = (c % (BK / 8)) * 8;
+        const int64_t gn = n0 + nn, gk = k0 + kk;
+        if (vec && gn < a.N && gk + 8 <= kend) {
+          rb[e].u = *(const uint4*)(B + gn * a.sbn + gk);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            rb[e].h[i] = (gn < a.N && gk + i < kend) ? B[gn * a.sbn + gk + i] : (bf16_t)0;
+        }
+      } else {
+        const int kk = c / (BN / 8), nn = (c % (BN / 8)) * 8;
+        const int64_t gn = n0 + nn, gk = k0 + kk;
+        if (vec && gk < kend && gn + 8 <= a.N) {
+          rb[e].u = *(const uint4*)(B + gk * a.sbk + gn);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            rb[e].h[i] = (gk < kend && gn + i < a.N) ? B[gk * a.sbk + gn + i] : (bf16_t)0;
+        }
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < CA; ++e) {
+      const int c = tid + e * 256;
+      if (AK) {
+        const int mm = c / (BK / 8), kk = (c % (BK / 8)) * 8;
+        *(uint4*)&As[buf][mm * LDK + kk] = ra[e].u;
+      } else {
+        const int kk = c / (BM / 8), mm = (c % (BM / 8)) * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) As[buf][(mm + i) * LDK + kk] = ra[e].h[i];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+      const int c = tid + e * 256;
+      if (BKC) {
+        const int nn = c / (BK / 8), kk = (c % (BK / 8)) * 8;
+        *(uint4*)&Bs[buf][nn * LDK + kk] = rb[e].u;
+      } else {
+        const int kk = c / (BN / 8), nn = (c % (BN / 8)) * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Bs[buf][(nn + i) * LDK + kk] = rb[e].h[i];
+      }
+    }
+  };
+
+  f4_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  const int fr = lane & 15, fk = 8 * (lane >> 4);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 32) {
+      bf16x8_t af[TM], bfr[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        af[i] = *(const bf16x8_t*)&As[cur][(wm * WM + i * 16 + fr) * LDK + ks + fk];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        bfr[j] = *(const bf16x8_t*)&Bs[cur][(wn * WN + j * 16 + fr) * LDK + ks + fk];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+        const int64_t gn = n0 + wn * WN + j * 16 + (lane & 15);
+        if (gm < a.M && gn < a.N) store_out<OutT>(a, b, split, gm, gn, (double)acc[i][j][r]);
+      }
+}
+
+// Sums the split-K partials in split order and applies alpha / beta.
+template <typename PT, typename OutT>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const PT* __restrict__ part, int splits,
+                                                            int64_t batch, int64_t M, int64_t N,
+                                                            OutT* C, int64_t scm, int64_t scb,
+                                                            double alpha, double beta) {
+  const int64_t total = batch * M * N;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int s = 0; s < splits; ++s) acc += (double)part[s * total + idx];
+    const int64_t b = idx / (M * N), rem = idx % (M * N);
+    const int64_t m = rem / N, n = rem % N;
+    OutT* c = C + b * scb + m * scm + n;
+    double r = alpha * acc;
+    if (beta != 0.0) r += beta * Conv<OutT>::to_f64(*c);
+    *c = Conv<OutT>::from_f64(r);
+  }
+}
+
+KArgs make_args(const Gemm& g, int BM, int BN, int BK) {
+  KArgs a;
+  a.M = g.M; a.N = g.N; a.K = g.K; a.batch = g.batch;
+  a.A = g.A; a.sam = g.sam; a.sak = g.sak; a.sab = g.sab;
+  a.B = g.B; a.sbk = g.sbk; a.sbn = g.sbn; a.sbb = g.sbb;
+  a.C = g.C; a.scm = g.scm; a.scb = g.scb;
+  a.alpha = g.alpha; a.beta = g.beta;
+  int splits = std::max(1, g.splits);
+  int64_t kchunk = (g.K + splits - 1) / splits;
+  kchunk = std::max<int64_t>(BK, (kchunk + BK - 1) / BK * BK);
+  splits = (int)std::max<int64_t>(1, (g.K + kchunk - 1) / kchunk);
+  a.splits = splits;
+  a.kchunk = g.K > 0 ? kchunk : 1;
+  a.partial = g.partial;
+  a.tiles_m = (g.M + BM - 1) / BM;
+  a.tiles_n = (g.N + BN - 1) / BN;
+  a.vec_ok = 0;
+  return a;
+}
+
+void check_operand_strides(const Gemm& g) {
+  if (g.sak != 1 && g.sam != 1) throw std::invalid_argument("gemm: A has no unit stride");
+  if (g.sbk != 1 && g.sbn != 1) throw std::invalid_argument("gemm: B has no unit stride");
+  if (g.M < 0 || g.N < 0 || g.K < 0 || g.batch < 0) throw std::invalid_argument("gemm: negative size");
+}
+
+template <typename PT, typename OutT>
+void launch_reduce(const KArgs& a, hipStream_t s) {
+  const int64_t total = a.batch * a.M * a.N;
+  int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL((splitk_reduce_kernel<PT, OutT>), dim3((unsigned)blocks), dim3(256), 0, s,
+                     (const PT*)a.partial, a.splits, a.batch, a.M, a.N, (OutT*)a.C, a.scm, a.scb,
+                     a.alpha, a.beta);
+  CPPPL_LAUNCH_CHECK("splitk_reduce");
+}
+
+}  // namespace
+
+int choose_splits(int64_t tiles, int64_t K, int64_t target_blocks, int64_t min_k, int max_splits) {
+  if (tiles <= 0 || K <= 0) return 1;
+  int64_t s = (target_blocks + tiles - 1) / tiles;
+  s = std::min<int64_t>(s, std::max<int64_t>(1, K / std::max<int64_t>(1, min_k)));
+  s = std::min<int64_t>(s, max_splits);
+  return (int)std::max<int64_t>(1, s);
+}
+
+int64_t gemm_tiles_f64(int64_t M, int64_t N) { return ((M + 63) / 64) * ((N + 63) / 64); }
+int64_t gemm_tiles_bf16(int64_t M, int64_t N) { return ((M + 127) / 128) * ((N + 127) / 128); }
+
+void gemm_f64(const Gemm& g, hipStream_t s) {
+  check_operand_strides(g);
+  if (g.ctype != DType::F64) throw std::invalid_argument("gemm_f64: output must be FP64");
+  constexpr int BM = 64, BN = 64;
+  KArgs a = make_args(g, BM, BN, 16);
+  if (a.splits > 1 && !a.partial) throw std::invalid_argument("gemm_f64: split-K needs a partial buffer");
+  const int64_t blocks = a.tiles_m * a.tiles_n * a.batch * a.splits;
+  if (blocks == 0) return;
+  if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_f64: grid too large");
+  const bool ak = g.sak == 1, bk = g.sbk == 1;
+  dim3 grid((unsigned)blocks), block(256);
+  if (ak && bk) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, true>), grid, block, 0, s, a);
+  else if (ak && !bk) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, false>), grid, block, 0, s, a);
+  else if (!ak && bk) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, false>), grid, block, 0, s, a);
+  CPPPL_LAUNCH_CHECK("gemm_f64");
+  if (a.splits > 1) launch_reduce<double, double>(a, s);
+}
+
+template <bool AK, bool BKC>
+static void launch_bf16(const KArgs& a, DType ct, dim3 grid, hipStream_t s) {
+  constexpr int BM = 128, BN = 128;
+  if (ct == DType::F32 || a.splits > 1)
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, AK, BKC, float>), grid, dim3(256), 0, s, a);
+  else if (ct == DType::BF16)
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, AK, BKC, bf16_t>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, AK, BKC, double>), grid, dim3(256), 0, s, a);
+}
+
+void gemm_bf16(const Gemm& g, hipStream_t s) {
+  check_operand_strides(g);
+  if (g.beta != 0.0 && g.splits <= 1) throw std::invalid_argument("gemm_bf16: beta must be 0");
+  constexpr int BM = 128, BN = 128;
+  KArgs a = make_args(g, BM, BN, 64);
+  if (a.splits > 1 && !a.partial) throw std::invalid_argument("gemm_bf16: split-K needs a partial buffer");
+  const bool ak = g.sak == 1, bk = g.sbk == 1;
+  // 16-byte vector loads need 16-byte aligned rows along the contiguous index.
+  auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  const int64_t sa_row = ak ? g.sam : g.sak, sb_row = bk ? g.sbn : g.sbk;
+  a.vec_ok = (al(g.A) && al(g.B) && sa_row % 8 == 0 && sb_row % 8 == 0 && g.sab % 8 == 0 &&
+              g.sbb % 8 == 0) ? 1 : 0;
+  const int64_t blocks = a.tiles_m * a.tiles_n * a.batch * a.splits;
+  if (blocks == 0) return;
+  if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_bf16: grid too large");
+  dim3 grid((unsigned)blocks);
+  if (ak && bk) launch_bf16<true, true>(a, g.ctype, grid, s);
+  else if (ak && !bk) launch_bf16<true, false>(a, g.ctype, grid, s);
+  else if (!ak && bk) launch_bf16<false, true>(a, g.ctype, grid, s);
+  else launch_bf16<false, false>(a, g.ctype, grid, s);
+  CPPPL_LAUNCH_CHECK("gemm_bf16");
+  if (a.splits > 1) {
+    if (g.ctype == DType::F32) launch_reduce<float, float>(a, s);
+    else if (g.ctype == DType::BF16) launch_reduce<float, bf16_t>(a, s);
+    else launch_reduce<float, double>(a, s);
+  }
+}
+
+}  // namespace cpppl

@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI: the library builds, loads without a GPU and
+exports every function its headers declare; host-only calls behave."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2503_10380_amd as cp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    return set(re.findall(r"CPPPL_API\s+[\w\s\*]+?\b(cpppl_\w+)\s*\(", text))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(cp.LIB_PATH):
+        from paper_2503_10380_amd import build
+        build.build()
+    return cp.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared("cpppl.h") | _declared("cpppl_testing.h")
+    assert len(names) >= 30
+    out = subprocess.run(["nm", "-D", "--defined-only", cp.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = sorted(names - exported)
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+    # nothing else leaks out of the library under the cpppl_ prefix
+    assert {e for e in exported if e.startswith("cpppl_")} == names
+
+
+def test_binding_covers_header(lib):
+    assert set(cp.header_symbols()) == _declared("cpppl.h")
+
+
+def test_workspace_size_host_only(lib):
+    size = C.c_size_t()
+    d = cp.Dims(4, 16, 48, 32)
+    assert lib.cpppl_workspace_size(C.byref(d), cp.FP64, C.byref(size)) == 0
+    s64 = size.value
+    assert lib.cpppl_workspace_size(C.byref(d), cp.BF16, C.byref(size)) == 0
+    assert size.value > s64 > 0
+    bad = cp.Dims(4, 0, 48, 32)
+    assert lib.cpppl_workspace_size(C.byref(bad), cp.FP64, C.byref(size)) == -1
+    big = cp.Dims(4, 16, 48, 5000)
+    assert lib.cpppl_workspace_size(C.byref(big), cp.FP64, C.byref(size)) == -1
+    assert lib.cpppl_workspace_size(C.byref(d), 7, C.byref(size)) == -1
+    c3 = cp.Dims(32, 256, 768, 1024)
+    assert lib.cpppl_workspace_size(C.byref(c3), cp.BF16, C.byref(size)) == 0
+    assert size.value < 16 * 2 ** 30  # C3 fits comfortably in one GPU's HBM
+
+
+def test_status_strings_and_null_handling(lib):
+    assert lib.cpppl_status_str(0) == b"ok"
+    assert lib.cpppl_status_str(-5).startswith(b"normal equations")
+    assert lib.cpppl_destroy(None) == -1
+    assert lib.cpppl_als(None, None, None) == -1
+    d = cp.Dims(4, 16, 48, 32)
+    assert lib.cpppl_ws_in_dim(C.byref(d)) == 2 * (2 * 4 + 2 * 16)
+    assert lib.cpppl_ws_out_dim(C.byref(d)) == 2 * 4 + 2 * 16

@@ -1,0 +1,124 @@
+"""GPU checks of the kernel layer through the test hooks: the matrix-core GEMM
+in both precisions and every operand layout (ragged tiles, batches, split-K),
+and the blocked Cholesky solve, against numpy in FP64."""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env(lib):
+    import torch
+    L = lib.load_library()
+    L.cpppl_test_gemm.restype = C.c_int
+    L.cpppl_test_gemm.argtypes = [C.c_int] + [C.c_int64] * 4 + [C.c_void_p] + [C.c_int64] * 3 + \
+        [C.c_void_p] + [C.c_int64] * 3 + [C.c_void_p] + [C.c_int64] * 2 + \
+        [C.c_int, C.c_double, C.c_double, C.c_int, C.c_void_p, C.c_void_p]
+    L.cpppl_test_spd_solve.restype = C.c_int
+    L.cpppl_test_spd_solve.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]
+    return L, torch
+
+
+def _operand(torch, rng, batch, rows, cols, unit_dim, dtype, pad=3):
+    """Logical X[b][rows][cols] stored with unit stride along `unit_dim`."""
+    x = rng.standard_normal((batch, rows, cols))
+    if dtype == "bf16":
+        x = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    if unit_dim == 1:
+        ld = cols + pad
+        store = np.zeros((batch, rows, ld))
+        store[:, :, :cols] = x
+        s_row, s_col = ld, 1
+    else:
+        ld = rows + pad
+        store = np.zeros((batch, cols, ld))
+        store[:, :, :rows] = x.transpose(0, 2, 1)
+        s_row, s_col = 1, ld
+    sb = store.shape[1] * store.shape[2]
+    t = torch.tensor(store.reshape(-1))
+    if dtype == "bf16":
+        t = t.to(torch.bfloat16)
+    return x, t.cuda(), s_row, s_col, sb
+
+
+CASES = [
+    # (M, N, K, batch, splits)
+    (70, 45, 37, 1, 1),
+    (129, 131, 200, 2, 1),
+    (64, 64, 16, 1, 1),
+    (33, 257, 300, 1, 4),
+    (5, 3, 1, 3, 1),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "bf16"])
+@pytest.mark.parametrize("ak", [True, False])
+@pytest.mark.parametrize("bk", [True, False])
+@pytest.mark.parametrize("case", CASES)
+def test_gemm_layouts(env, dtype, ak, bk, case):
+    L, torch = env
+    M, N, K, batch, splits = case
+    _say(f"gemm {dtype} ak={ak} bk={bk} case={case}")
+    rng = np.random.default_rng(hash((M, N, K, batch, ak, bk)) % 2 ** 32)
+    a, ta, sam, sak, sab = _operand(torch, rng, batch, M, K, 1 if ak else 0, dtype)
+    b, tb, sbk, sbn, sbb = _operand(torch, rng, batch, K, N, 0 if bk else 1, dtype)
+    c0 = rng.standard_normal((batch, M, N))
+    beta = 0.5 if dtype == "f64" else 0.0
+    alpha = -1.25 if dtype == "f64" else 1.0
+    tc = torch.tensor(c0.reshape(-1)).cuda()
+    part = torch.zeros(max(1, splits * batch * M * N), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    st = L.cpppl_test_gemm(0 if dtype == "f64" else 1, M, N, K, batch,
+                           ta.data_ptr(), sam, sak, sab, tb.data_ptr(), sbk, sbn, sbb,
+                           tc.data_ptr(), N, M * N, 0, alpha, beta, splits, part.data_ptr(), stream)
+    assert st == 0
+    want = alpha * np.einsum("bmk,bkn->bmn", a, b) + beta * c0
+    got = tc.cpu().numpy().reshape(batch, M, N)
+    err = np.abs(got - want).max() / max(1e-300, np.abs(want).max())
+    tol = 1e-13 if dtype == "f64" else 5e-5
+    assert err <= tol, err
+
+
+@pytest.mark.parametrize("R,n", [(1, 3), (17, 5), (64, 64), (65, 7), (300, 130), (1024, 256)])
+def test_cholesky_solve(env, R, n):
+    L, torch = env
+    _say(f"spd_solve R={R} n={n}")
+    rng = np.random.default_rng(R)
+    f = rng.standard_normal((R + 5, R))
+    w = f.T @ f + 0.1 * np.eye(R)
+    x = rng.standard_normal((R, n))
+    tw = torch.tensor(w).cuda()
+    tx = torch.tensor(x).cuda()
+    ds = torch.zeros(((R + 63) // 64) * 64 * 64, dtype=torch.float64, device="cuda")
+    status = torch.zeros(4, dtype=torch.int32, device="cuda")
+    st = L.cpppl_test_spd_solve(tw.data_ptr(), R, tx.data_ptr(), n, ds.data_ptr(),
+                                status.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert st == 0 and int(status[0]) == 0
+    want = np.linalg.solve(w, x)
+    got = tx.cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max() * np.linalg.cond(w) ** 0.5
+
+
+def test_cholesky_flags_indefinite(env):
+    L, torch = env
+    R = 70
+    w = np.eye(R)
+    w[40, 40] = -1.0
+    tw = torch.tensor(w).cuda()
+    tx = torch.ones((R, 2), dtype=torch.float64, device="cuda")
+    ds = torch.zeros(2 * 64 * 64, dtype=torch.float64, device="cuda")
+    status = torch.zeros(4, dtype=torch.int32, device="cuda")
+    st = L.cpppl_test_spd_solve(tw.data_ptr(), R, tx.data_ptr(), 2, ds.data_ptr(),
+                                status.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert st == 0 and int(status[0]) == 1
+    assert torch.isfinite(tx).all()

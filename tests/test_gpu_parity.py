@@ -1,0 +1,225 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+MTTKRPs are compared per mode for identical factors (relative Frobenius error
+<= 1e-10, the FP64 target); ALS trajectories are compared sweep by sweep from
+the same starting factors; ||R||^2, E_exact, E_CP and the fit scalars against
+the oracle's explicit tensors.  Sizes span several GEMM tiles with ragged tails.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SMALL = {
+    "C1": synth.CONFIGS["C1"],
+    "ragged_xlt_v": synth.custom_config(3, 10, 7, 5, name="o3v10X7R5"),
+    "ragged_tiles": synth.custom_config(5, 33, 70, 70, name="o5v33X70R70"),
+    "odd": synth.custom_config(7, 19, 61, 131, name="o7v19X61R131"),
+}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+_CACHE = {}
+
+
+def _problem(cfg):
+    if cfg.name not in _CACHE:
+        inp = synth.make_inputs(cfg)
+        r = oracle.form_r(inp.t, inp.b_vv)
+        _CACHE[cfg.name] = (inp, r)
+    return _CACHE[cfg.name]
+
+
+def _ctx(lib, cfg, inp, precision="fp64"):
+    ctx = lib.Context(cfg.o, cfg.v, cfg.nx, cfg.rank, precision)
+    ctx.load_t2(inp.t)
+    ctx.load_df(inp.b_vv)
+    return ctx
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_norm_r2_and_energy_exact(lib, name):
+    cfg = SMALL[name]
+    _say(f"norm_r2 {name}")
+    inp, r = _problem(cfg)
+    ctx = _ctx(lib, cfg, inp)
+    n2, e = ctx.norm_r2()
+    n2_o, e_o = oracle.norm_r2_and_energy(r, inp.t)
+    assert n2 == pytest.approx(n2_o, rel=1e-12)
+    assert e == pytest.approx(e_o, rel=1e-12)
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_mttkrp_fp64(lib, name, mode):
+    cfg = SMALL[name]
+    _say(f"mttkrp fp64 {name} mode {mode}")
+    inp, r = _problem(cfg)
+    fs = synth.init_factors(cfg)
+    ctx = _ctx(lib, cfg, inp)
+    ctx.set_factors(*fs)
+    got = ctx.mttkrp(mode)
+    want = oracle.mttkrp(r, fs, mode)
+    assert _rel(got, want) <= 1e-10
+
+
+def test_set_get_factors_roundtrip(lib):
+    cfg = SMALL["odd"]
+    inp, _ = _problem(cfg)
+    fs = synth.init_factors(cfg)
+    lam = np.linspace(0.5, 1.5, cfg.rank)
+    ctx = _ctx(lib, cfg, inp)
+    ctx.set_factors(*fs, lam)
+    out = ctx.get_factors()
+    for a, b in zip(out, (*fs, lam)):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_fit_and_energy_at_given_factors(lib, name):
+    cfg = SMALL[name]
+    _say(f"fit/energy {name}")
+    inp, r = _problem(cfg)
+    fs = synth.init_factors(cfg)
+    lam = np.linspace(0.5, 1.5, cfg.rank)
+    ctx = _ctx(lib, cfg, inp)
+    ctx.set_factors(*fs, lam)
+    fit, inner, cp2 = ctx.fit()
+    cp = oracle.cp_full(fs, lam)
+    assert inner == pytest.approx(np.sum(r * cp), rel=1e-11)
+    assert cp2 == pytest.approx(np.sum(cp * cp), rel=1e-11)
+    want_fit = 1 - np.linalg.norm(r - cp) / np.linalg.norm(r)
+    assert fit == pytest.approx(want_fit, rel=1e-9, abs=1e-9)
+    assert ctx.energy() == pytest.approx(np.sum(cp * inp.t), rel=1e-11)
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_als_trajectory_fp64(lib, name):
+    cfg = SMALL[name]
+    _say(f"als trajectory {name}")
+    inp, r = _problem(cfg)
+    fs = synth.init_factors(cfg)
+    n2 = float(np.sum(r * r))
+    f_o, lam_o, hist = oracle.cp_als(r, fs, 10, norm_r2=n2, t=inp.t)
+    ctx = _ctx(lib, cfg, inp)
+    ctx.set_factors(*fs)
+    rep = ctx.als(10, energy=True)
+    assert rep["sweeps"] == 10
+    np.testing.assert_allclose(rep["fit_hist"], hist["fit"], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(rep["eta_hist"], hist["eta"], rtol=1e-7, atol=1e-9)
+    assert rep["loss"] == pytest.approx(hist["loss"][-1], rel=1e-8)
+    assert rep["energy_cp"] == pytest.approx(hist["energy"][-1], rel=1e-8)
+    fi, fj, fa, fb, lam = ctx.get_factors()
+    for g_, w_ in zip((fi, fj, fa, fb), f_o):
+        assert _rel(g_, w_) <= 1e-7
+    assert _rel(lam, lam_o) <= 1e-7
+
+
+def test_als_stop_rule_fit(lib):
+    cfg = SMALL["C1"]
+    inp, r = _problem(cfg)
+    fs = synth.init_factors(cfg)
+    _, _, hist = oracle.cp_als(r, fs, 50, stop_rule=1, tol=1e-3)
+    ctx = _ctx(lib, cfg, inp)
+    ctx.set_factors(*fs)
+    rep = ctx.als(50, stop_rule=1, tol=1e-3)
+    assert rep["sweeps"] == len(hist["fit"])
+
+
+def test_ridge_retry_matches_oracle(lib):
+    cfg = SMALL["ragged_tiles"]
+    _say("ridge retry")
+    inp, r = _problem(cfg)
+    fs = [np.array(f) for f in synth.init_factors(cfg)]
+    fs[3][:, 0] = 0.0  # a zero beta column makes W of the first update singular
+    _, _, hist = oracle.cp_als(r, fs, 3)
+    assert hist["retries"] > 0
+    ctx = _ctx(lib, cfg, inp)
+    ctx.set_factors(*fs)
+    rep = ctx.als(3)
+    assert rep["ridge_retries"] == hist["retries"]
+    np.testing.assert_allclose(rep["fit_hist"], hist["fit"], rtol=0, atol=1e-9)
+
+
+def test_planted_cp_tensor(lib):
+    cfg = synth.custom_config(6, 20, 30, 24, name="planted")
+    _say("planted")
+    pf = synth.planted_factors(cfg, 12)
+    true, lamp = pf[:4], pf[4]
+    ctx = lib.Context(cfg.o, cfg.v, cfg.nx, cfg.rank)
+    ctx.load_planted(*true, lamp)
+    r = oracle.cp_full(true, lamp)
+    n2, e = ctx.norm_r2()
+    assert n2 == pytest.approx(np.sum(r * r), rel=1e-12)
+    assert np.isnan(e)
+    fs = synth.init_factors(cfg)
+    ctx.set_factors(*fs)
+    for mode in range(4):
+        assert _rel(ctx.mttkrp(mode), oracle.mttkrp(r, fs, mode)) <= 1e-10
+    _, _, hist = oracle.cp_als(r, fs, 5)
+    rep = ctx.als(5)
+    np.testing.assert_allclose(rep["fit_hist"], hist["fit"], rtol=0, atol=1e-9)
+
+
+def test_planted_recovery_from_perturbed_start(lib):
+    cfg = synth.custom_config(16, 128, 384, 512, name="C2planted")
+    _say("planted C2 recovery")
+    pf = synth.planted_factors(cfg, 512)
+    true, lamp = pf[:4], pf[4]
+    ctx = lib.Context(cfg.o, cfg.v, cfg.nx, cfg.rank)
+    ctx.load_planted(*true, lamp)
+    rng = np.random.default_rng(0)
+    start = [f + 1e-3 * rng.standard_normal(f.shape) for f in true]
+    ctx.set_factors(*start)
+    rep = ctx.als(10)
+    assert rep["fit"] >= 1 - 1e-7
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_mttkrp_fp64_c2(lib, mode):
+    cfg = synth.CONFIGS["C2"]
+    _say(f"mttkrp fp64 C2 mode {mode}")
+    inp, r = _problem(cfg)
+    fs = synth.init_factors(cfg)
+    ctx = _ctx(lib, cfg, inp)
+    ctx.set_factors(*fs)
+    assert _rel(ctx.mttkrp(mode), oracle.mttkrp(r, fs, mode)) <= 1e-10
+
+
+@pytest.mark.parametrize("cfg_name", ["C3", "C5"])
+def test_full_size_rank1_t2_closed_form(lib, cfg_name):
+    """At the full workload sizes: T2 = u w p q makes R an exact rank-X CP tensor
+    whose MTTKRPs have a closed form (no O(N^6) work), in FP64 and BF16."""
+    cfg = synth.CONFIGS[cfg_name]
+    _say(f"closed form {cfg_name}")
+    rng = np.random.default_rng(cfg.cfg_id)
+    b = rng.standard_normal((cfg.nx, cfg.v, cfg.v)) / np.sqrt(cfg.nx)
+    t, (u, w, p, q) = synth.rank1_t2(cfg)
+    cf = oracle.rank1_closed_form(u, w, p, q, b)
+    fs = synth.init_factors(cfg)
+    for prec, tol in (("fp64", 1e-10), ("bf16", 3e-2)):
+        ctx = lib.Context(cfg.o, cfg.v, cfg.nx, cfg.rank, prec)
+        ctx.load_t2(t)
+        ctx.load_df(b)
+        ctx.set_factors(*fs)
+        for mode in range(4):
+            want = oracle.planted_mttkrp(cf, np.ones(cfg.nx), fs, mode)
+            err = _rel(ctx.mttkrp(mode), want)
+            _say(f"  {prec} mode {mode} rel err {err:.3e}")
+            assert err <= tol
+        ctx.close()
+        del ctx
