@@ -83,8 +83,9 @@ enum {
   CPPPL_T_M = 3,       /* M = B . Z, split-K         (S5 / S7) */
   CPPPL_T_G = 4,       /* per-r G = Y_a^T Y_b        (S8) */
   CPPPL_T_H = 5,       /* H = t . G, split-K         (S9) */
-  CPPPL_T_SOLVE = 6,   /* Grams, W, Cholesky, solve, normalise (S6, S10) */
+  CPPPL_T_SOLVE = 6,   /* occupied reductions of H, Grams, W, Cholesky, solve, normalise */
   CPPPL_T_FIT = 7,     /* fit, eta, energy scalars (S11, S12) */
+  CPPPL_T_INV = 8,     /* W and its inverse (side stream for alpha, beta, gamma: overlapped) */
   CPPPL_T_COUNT = 16
 };
 

@@ -61,6 +61,22 @@ def form_r(t: np.ndarray, b_vv: np.ndarray, block: int | None = None,
     return out
 
 
+def form_r_pairs(t: np.ndarray, b_vv: np.ndarray, occ: int) -> np.ndarray:
+    """R restricted to i, j < occ, one occupied pair at a time from eq. dfB
+    (no (ac|bd) tensor): U^X = B^X T_ij with T_ij[c, d] = t_ijcd, then
+    R_ij[a, b] = sum_{X, d} U^X[a, d] B^X[b, d].  Returns (occ, occ, v, v)."""
+    nx, v, _ = b_vv.shape
+    bstack = b_vv.reshape(nx * v, v)                        # rows (X, a), cols c
+    bperm = b_vv.transpose(1, 0, 2).reshape(v, nx * v)      # rows b, cols (X, d)
+    out = np.empty((occ, occ, v, v))
+    for i in range(occ):
+        for j in range(occ):
+            u = (bstack @ t[i, j]).reshape(nx, v, v)          # U[X, a, d]
+            ut = u.transpose(1, 0, 2).reshape(v, nx * v)      # rows a, cols (X, d)
+            out[i, j] = ut @ bperm.T
+    return out
+
+
 def form_r_einsum(t: np.ndarray, b_vv: np.ndarray) -> np.ndarray:
     """Second route to R (tiny sizes only): one einsum over X, c, d."""
     return np.einsum("xac,xbd,ijcd->ijab", b_vv, b_vv, t, optimize=True)

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "cpppl.h")
 FP64, BF16 = 0, 1
 PRECISIONS = {"fp64": FP64, "bf16": BF16}
 WS_PLAIN, WS_LEARNED, WS_FIRST_ORDER = 0, 1, 2
-T_CLASSES = ["kr_t2", "y", "z", "m", "g", "h", "solve", "fit"]
+T_CLASSES = ["kr_t2", "y", "z", "m", "g", "h", "solve", "fit", "inv"]
 
 STATUS = {0: "ok", -1: "E_ARG", -2: "E_STATE", -3: "E_HIP", -4: "E_NOMEM", -5: "E_NOT_SPD",
           -6: "E_NONFINITE", -7: "E_UNSUPPORTED"}

@@ -77,8 +77,8 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   p.lamp = add(R * 8);
   p.wsLam = add(R * 8);
   p.Cp = add((size_t)R * R * 8);
-  p.L = add((size_t)R * R * 8);
-  p.Dsave = add((size_t)diag_save_elems(R) * 8);
+  p.invA = add((size_t)R * R * 8);
+  p.invB = add((size_t)R * R * 8);
   const int64_t nmax = std::max(o, v);
   p.MT = add((size_t)nmax * R * 8);
   p.stage = add((size_t)std::max<int64_t>(nmax * R, R * R) * 8);
@@ -133,17 +133,18 @@ hipEvent_t next_event(cpppl_ctx* c) {
 struct Span {
   cpppl_ctx* c;
   int cls;
+  hipStream_t st;
   hipEvent_t a = nullptr;
-  Span(cpppl_ctx* c_, int cls_) : c(c_), cls(cls_) {
+  Span(cpppl_ctx* c_, int cls_, hipStream_t s_ = nullptr) : c(c_), cls(cls_), st(s_ ? s_ : c_->stream) {
     if (c->timing) {
       a = next_event(c);
-      CPPPL_HIP(hipEventRecord(a, c->stream));
+      CPPPL_HIP(hipEventRecord(a, st));
     }
   }
   ~Span() noexcept(false) {
     if (c->timing && a) {
       hipEvent_t b = next_event(c);
-      CPPPL_HIP(hipEventRecord(b, c->stream));
+      CPPPL_HIP(hipEventRecord(b, st));
       c->segs.push_back({cls, a, b});
     }
   }
@@ -268,7 +269,7 @@ void compute_H(cpppl_ctx* c, const Path& P) {
 }
 
 void compute_occ(cpppl_ctx* c, int mode) {
-  Span sp(c, CPPPL_T_H);
+  Span sp(c, CPPPL_T_SOLVE);
   const int64_t o = c->d.o, R = c->d.rank;
   const double* other = c->at<double>(c->plan.FT[mode == 0 ? 1 : 0]);
   occ_reduce(c->at<double>(c->plan.HT), other, c->at<double>(c->plan.MT), o, R, mode == 0 ? 0 : 1,
@@ -326,7 +327,10 @@ void copy_d2d(cpppl_ctx* c, size_t dst, size_t src, size_t bytes) {
   CPPPL_HIP(hipMemcpyAsync(c->at(dst), c->at(src), bytes, hipMemcpyDeviceToDevice, c->stream));
 }
 
-void sync(cpppl_ctx* c) { CPPPL_HIP(hipStreamSynchronize(c->stream)); }
+void sync(cpppl_ctx* c) {
+  CPPPL_HIP(hipStreamSynchronize(c->stream));
+  CPPPL_HIP(hipStreamSynchronize(c->side));
+}
 
 int read_status(cpppl_ctx* c) {
   CPPPL_HIP(hipMemcpyAsync(c->host_status, c->at(c->plan.status), 16 * sizeof(int),
@@ -335,11 +339,11 @@ int read_status(cpppl_ctx* c) {
   return c->host_status[0];
 }
 
-// F_m <- M W^{-1} with W = *_{k != m} Gram_k, normalise, refresh Gram_m.
-// careful: synchronise and retry with a ridge shift on failure.  Returns retries.
-int solve_mode(cpppl_ctx* c, int m, bool careful) {
-  Span sp(c, CPPPL_T_SOLVE);
-  const int64_t n = nmode(c->d, m), R = c->d.rank;
+// -W_m^{-1}, W_m = *_{k != m} Gram_k, on stream `st` into c->inv.  careful:
+// synchronise and retry with a ridge shift while a pivot fails.  Returns retries.
+int prepare_inverse(cpppl_ctx* c, int m, hipStream_t st, bool careful) {
+  Span sp(c, CPPPL_T_INV, st);
+  const int64_t R = c->d.rank;
   const Plan& p = c->plan;
   const double* G[3];
   int q = 0;
@@ -347,22 +351,49 @@ int solve_mode(cpppl_ctx* c, int m, bool careful) {
     if (k != m) G[q++] = c->at<double>(p.gram[k]);
   int retries = 0;
   for (int attempt = 0; attempt < 6; ++attempt) {
-    hadamard(G[0], G[1], G[2], c->at<double>(p.L), R * R, c->stream);
-    if (attempt > 0) add_ridge(c->at<double>(p.L), R, 1e-14 * std::pow(100.0, attempt - 1), c->stream);
-    if (careful) zero_ints(c->at<int>(p.status), 1, c->stream);
-    cholesky(c->at<double>(p.L), R, c->at<double>(p.Dsave), c->at<int>(p.status), c->stream);
+    hadamard(G[0], G[1], G[2], c->at<double>(p.invA), R * R, st);
+    if (attempt > 0) add_ridge(c->at<double>(p.invA), R, 1e-14 * std::pow(100.0, attempt - 1), st);
+    if (careful) zero_ints(c->at<int>(p.status), 1, st);
+    c->inv = spd_inverse_neg(c->at<double>(p.invA), c->at<double>(p.invB), R, c->at<int>(p.status), st);
     if (!careful) break;
+    CPPPL_HIP(hipStreamSynchronize(st));
     if (read_status(c) == 0) break;
     retries = attempt + 1;
     if (attempt == 5) throw StatusError(CPPPL_E_NOT_SPD, "W is not positive definite after 5 ridge retries");
   }
-  copy_d2d(c, p.FT[m], p.MT, (size_t)(n * R) * 8);
-  spd_solve(c->at<double>(p.L), c->at<double>(p.Dsave), R, c->at<double>(p.FT[m]), n, c->stream);
+  return retries;
+}
+
+// F_m^T = W^{-1} M^T (one GEMM), normalise the rows into lambda, refresh Gram_m.
+void apply_inverse(cpppl_ctx* c, int m) {
+  Span sp(c, CPPPL_T_SOLVE);
+  const int64_t n = nmode(c->d, m), R = c->d.rank;
+  const Plan& p = c->plan;
+  Gemm g;
+  g.M = R; g.N = n; g.K = R;
+  g.A = c->inv; g.sam = R; g.sak = 1;
+  g.B = c->at(p.MT); g.sbk = n; g.sbn = 1;
+  g.C = c->at(p.FT[m]); g.scm = n; g.ctype = DType::F64; g.alpha = -1.0;
+  gemm_f64(g, c->stream);
   row_normalize(c->at<double>(p.FT[m]), R, n, c->at<double>(p.lam), c->stream);
   compute_gram(c, m);
   refresh_lowp(c, m);
-  return retries;
 }
+
+int solve_mode(cpppl_ctx* c, int m, bool careful) {
+  const int r = prepare_inverse(c, m, c->stream, careful);
+  apply_inverse(c, m);
+  return r;
+}
+
+// Start -W_m^{-1} on the side stream once the main stream has produced the Grams it needs.
+void fork_inverse(cpppl_ctx* c, int m) {
+  CPPPL_HIP(hipEventRecord(c->ev_main, c->stream));
+  CPPPL_HIP(hipStreamWaitEvent(c->side, c->ev_main, 0));
+  prepare_inverse(c, m, c->side, false);
+  CPPPL_HIP(hipEventRecord(c->ev_side, c->side));
+}
+void join_inverse(cpppl_ctx* c) { CPPPL_HIP(hipStreamWaitEvent(c->stream, c->ev_side, 0)); }
 
 // The MTTKRP of `mode` at the current factors into MT (R x n).
 void mttkrp_into_MT(cpppl_ctx* c, const Path& P, int mode) {
@@ -439,34 +470,63 @@ void cp2_current(cpppl_ctx* c, double* out) {
                         c->at<double>(c->plan.rowbuf), out, c->stream);
 }
 
-// One ALS sweep on path P; returns ridge retries.
+// One ALS sweep on path P; returns ridge retries.  Outside careful mode the
+// inverse of W for alpha, beta and gamma runs on the side stream while the
+// main stream evaluates that factor's MTTKRP.
 int sweep(cpppl_ctx* c, const Path& P, bool careful) {
   const Plan& p = c->plan;
   int retries = 0;
-  if (c->planted) {
-    for (int m : {2, 3, 0, 1}) {
-      planted_mttkrp(c, m);
-      retries += solve_mode(c, m, careful);
+  if (c->planted || careful) {
+    if (c->planted) {
+      for (int m : {2, 3, 0, 1}) {
+        planted_mttkrp(c, m);
+        retries += solve_mode(c, m, careful);
+      }
+    } else {
+      compute_tau(c, P);
+      if (!c->ybeta_valid || c->ybeta_dt != P.dt) compute_Y(c, P, 3, p.Yb);
+      compute_Z(c, P, 2);
+      compute_M(c, P);
+      retries += solve_mode(c, 2, true);
+      compute_Y(c, P, 2, p.Ya);
+      compute_Z(c, P, 3);
+      compute_M(c, P);
+      retries += solve_mode(c, 3, true);
+      compute_Y(c, P, 3, p.Yb);
+      compute_G(c, P);
+      compute_H(c, P);
+      compute_occ(c, 0);
+      retries += solve_mode(c, 0, true);
+      compute_occ(c, 1);
+      retries += solve_mode(c, 1, true);
+      c->ybeta_valid = true;
+      c->ybeta_dt = P.dt;
     }
   } else {
+    fork_inverse(c, 2);
     compute_tau(c, P);
     if (!c->ybeta_valid || c->ybeta_dt != P.dt) compute_Y(c, P, 3, p.Yb);
     compute_Z(c, P, 2);
     compute_M(c, P);
-    retries += solve_mode(c, 2, careful);
+    join_inverse(c);
+    apply_inverse(c, 2);
+    fork_inverse(c, 3);
     compute_Y(c, P, 2, p.Ya);
     compute_Z(c, P, 3);
     compute_M(c, P);
-    retries += solve_mode(c, 3, careful);
+    join_inverse(c);
+    apply_inverse(c, 3);
+    fork_inverse(c, 0);
     compute_Y(c, P, 3, p.Yb);
     c->ybeta_valid = true;
     c->ybeta_dt = P.dt;
     compute_G(c, P);
     compute_H(c, P);
     compute_occ(c, 0);
-    retries += solve_mode(c, 0, careful);
+    join_inverse(c);
+    apply_inverse(c, 0);
     compute_occ(c, 1);
-    retries += solve_mode(c, 1, careful);
+    solve_mode(c, 1, false);
   }
   {
     Span sp(c, CPPPL_T_FIT);
@@ -602,15 +662,13 @@ void ws_mttkrp_into_MT(cpppl_ctx* c, DType dt, int mode) { mttkrp_into_MT(c, pat
 void ws_solve_no_update(cpppl_ctx* c, int mode, size_t out_off) {
   // out = MT W^{-1} with the current Grams (no normalisation, no state change)
   const int64_t n = nmode(c->d, mode), R = c->d.rank;
-  const Plan& p = c->plan;
-  const double* G[3];
-  int q = 0;
-  for (int k = 0; k < 4; ++k)
-    if (k != mode) G[q++] = c->at<double>(p.gram[k]);
-  hadamard(G[0], G[1], G[2], c->at<double>(p.L), R * R, c->stream);
-  cholesky(c->at<double>(p.L), R, c->at<double>(p.Dsave), c->at<int>(p.status), c->stream);
-  copy_d2d(c, out_off, p.MT, (size_t)(n * R) * 8);
-  spd_solve(c->at<double>(p.L), c->at<double>(p.Dsave), R, c->at<double>(out_off), n, c->stream);
+  prepare_inverse(c, mode, c->stream, false);
+  Gemm g;
+  g.M = R; g.N = n; g.K = R;
+  g.A = c->inv; g.sam = R; g.sak = 1;
+  g.B = c->at(c->plan.MT); g.sbk = n; g.sbn = 1;
+  g.C = c->at(out_off); g.scm = n; g.ctype = DType::F64; g.alpha = -1.0;
+  gemm_f64(g, c->stream);
 }
 void ws_init_after_factors(cpppl_ctx* c) { init_after_factors(c); }
 void ws_derive_t(cpppl_ctx* c) {
@@ -697,8 +755,14 @@ CPPPL_API cpppl_status cpppl_create(const cpppl_dims* dims, cpppl_precision prec
   c->plan = build_plan(*dims, prec);
   if (hipSetDevice(device) != hipSuccess ||
       hipHostMalloc((void**)&c->host_scal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->host_status, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->host_status, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming) != hipSuccess) {
     if (c->host_scal) (void)hipHostFree(c->host_scal);
+    if (c->host_status) (void)hipHostFree(c->host_status);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_main) (void)hipEventDestroy(c->ev_main);
     delete c;
     return CPPPL_E_HIP;
   }
@@ -726,6 +790,12 @@ CPPPL_API cpppl_status cpppl_destroy(cpppl_ctx* c) {
   if (!c) return CPPPL_E_ARG;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->ev_main) (void)hipEventDestroy(c->ev_main);
+  if (c->ev_side) (void)hipEventDestroy(c->ev_side);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   if (c->host_status) (void)hipHostFree(c->host_status);

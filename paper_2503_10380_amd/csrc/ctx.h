@@ -19,7 +19,7 @@ struct Plan {
   size_t t16, t16T, b16T, b16P;
   // factors (transposed, R x n), weights, snapshots, Grams
   size_t FT[4], FTprev[4], F16T[4], lam, lamprev;
-  size_t gram[4], cross[4], L, Dsave, MT, stage;
+  size_t gram[4], cross[4], invA, invB, MT, stage;
   // intermediates: one region [tau | Ya | Yb | Z]; G aliases Z
   size_t big, tau, Ya, Yb, Z;
   size_t big_bytes;
@@ -72,6 +72,10 @@ struct cpppl_ctx {
   bool ybeta_valid = false;
   cpppl::DType ybeta_dt = cpppl::DType::F64;
   bool ws_valid = false;      // warm-start snapshot (wsF) holds the factors before the last warm start
+
+  hipStream_t side = nullptr;     // inverse of W overlapped with the MTTKRP chain
+  hipEvent_t ev_main = nullptr, ev_side = nullptr;
+  double* inv = nullptr;          // buffer holding -W^{-1} of the last prepared mode
 
   double* host_scal = nullptr;  // pinned, S_COUNT doubles
   int* host_status = nullptr;   // pinned, 16 ints

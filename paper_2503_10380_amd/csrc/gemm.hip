@@ -22,6 +22,7 @@
 #include "gemm.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <stdexcept>
 
 namespace cpppl {
@@ -41,37 +42,42 @@ struct KArgs {
   int64_t kchunk;
   void* partial;
   int64_t tiles_m, tiles_n;
-  int vec_ok;
+  int vec_ok;    // 16-byte operand loads allowed
+  int cvec_ok;   // 16-byte result stores allowed
 };
 
-__device__ inline void tile_coords(int64_t lid, const KArgs& a, int64_t& b, int& split,
-                                   int64_t& tm, int64_t& tn) {
+struct Coords {
+  int64_t b, tm, tn;
+  int split;
+};
+
+__device__ __forceinline__ Coords tile_coords(int64_t lid, const KArgs& a) {
   const int64_t tiles = a.tiles_m * a.tiles_n;
   const int64_t t = lid % tiles;
   const int64_t bs = lid / tiles;
-  split = (int)(bs % a.splits);
-  b = bs / a.splits;
+  Coords c;
+  c.split = (int)(bs % a.splits);
+  c.b = bs / a.splits;
   if (a.tiles_m <= a.tiles_n) {
-    tm = t % a.tiles_m;
-    tn = t / a.tiles_m;
+    c.tm = t % a.tiles_m;
+    c.tn = t / a.tiles_m;
   } else {
-    tn = t % a.tiles_n;
-    tm = t / a.tiles_n;
+    c.tn = t % a.tiles_n;
+    c.tm = t / a.tiles_n;
   }
+  return c;
 }
 
 template <typename OutT>
-__device__ inline void store_out(const KArgs& a, int64_t b, int split, int64_t gm, int64_t gn,
-                                 double v) {
+__device__ __forceinline__ void store_out(const KArgs& a, const Coords& tc, int64_t gm, int64_t gn,
+                                          double v) {
   if (a.splits > 1) {
-    if constexpr (sizeof(OutT) == 8) {
-      ((double*)a.partial)[((int64_t)split * a.batch + b) * a.M * a.N + gm * a.N + gn] = v;
-    } else {
-      ((float*)a.partial)[((int64_t)split * a.batch + b) * a.M * a.N + gm * a.N + gn] = (float)v;
-    }
+    const int64_t off = ((int64_t)tc.split * a.batch + tc.b) * a.M * a.N + gm * a.N + gn;
+    if constexpr (sizeof(OutT) == 8) ((double*)a.partial)[off] = v;
+    else ((float*)a.partial)[off] = (float)v;
     return;
   }
-  OutT* c = (OutT*)a.C + b * a.scb + gm * a.scm + gn;
+  OutT* c = (OutT*)a.C + tc.b * a.scb + gm * a.scm + gn;
   double r = a.alpha * v;
   if (a.beta != 0.0) r += a.beta * Conv<OutT>::to_f64(*c);
   *c = Conv<OutT>::from_f64(r);
@@ -79,7 +85,7 @@ __device__ inline void store_out(const KArgs& a, int64_t b, int split, int64_t g
 
 // ------------------------------------------------------------------ FP64 ----
 template <int BM, int BN, bool AK, bool BKC>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs a) {
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const KArgs a) {
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
@@ -89,67 +95,62 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
-  int64_t b, tm, tn;
-  int split;
-  tile_coords(lid, a, b, split, tm, tn);
-  const int64_t m0 = tm * BM, n0 = tn * BN;
-  const int64_t kbeg = (int64_t)split * a.kchunk;
+  const Coords tc = tile_coords(xcd_remap(blockIdx.x, gridDim.x), a);
+  const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
+  const int64_t kbeg = (int64_t)tc.split * a.kchunk;
   const int64_t kend = min(a.K, kbeg + a.kchunk);
-  const double* A = (const double*)a.A + b * a.sab;
-  const double* B = (const double*)a.B + b * a.sbb;
+  const double* A = (const double*)a.A + tc.b * a.sab;
+  const double* B = (const double*)a.B + tc.b * a.sbb;
 
   double ra[EA], rb[EB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      const int idx = tid + e * 256;
-      const int mm = AK ? idx / BK : idx % BM;
-      const int kk = AK ? idx % BK : idx / BM;
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      ra[e] = (gm < a.M && gk < kend) ? A[AK ? (gm * a.sam + gk) : (gm + gk * a.sak)] : 0.0;
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      const int idx = tid + e * 256;
-      const int nn = BKC ? idx / BK : idx % BN;
-      const int kk = BKC ? idx % BK : idx / BN;
-      const int64_t gn = n0 + nn, gk = k0 + kk;
-      rb[e] = (gn < a.N && gk < kend) ? B[BKC ? (gn * a.sbn + gk) : (gn + gk * a.sbk)] : 0.0;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      const int idx = tid + e * 256;
-      const int mm = AK ? idx / BK : idx % BM;
-      const int kk = AK ? idx % BK : idx / BM;
-      As[buf][kk][mm] = ra[e];
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      const int idx = tid + e * 256;
-      const int nn = BKC ? idx / BK : idx % BN;
-      const int kk = BKC ? idx % BK : idx / BN;
-      Bs[buf][kk][nn] = rb[e];
-    }
-  };
-
   d4_t acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
+#define F64_GLOAD(k0)                                                                        \
+  {                                                                                          \
+    _Pragma("unroll") for (int e = 0; e < EA; ++e) {                                         \
+      const int idx = tid + e * 256;                                                         \
+      const int mm = AK ? idx / BK : idx % BM;                                               \
+      const int kk = AK ? idx % BK : idx / BM;                                               \
+      const int64_t gm = m0 + mm, gk = (k0) + kk;                                            \
+      ra[e] = (gm < a.M && gk < kend) ? A[AK ? (gm * a.sam + gk) : (gm + gk * a.sak)] : 0.0; \
+    }                                                                                        \
+    _Pragma("unroll") for (int e = 0; e < EB; ++e) {                                         \
+      const int idx = tid + e * 256;                                                         \
+      const int nn = BKC ? idx / BK : idx % BN;                                              \
+      const int kk = BKC ? idx % BK : idx / BN;                                              \
+      const int64_t gn = n0 + nn, gk = (k0) + kk;                                            \
+      rb[e] = (gn < a.N && gk < kend) ? B[BKC ? (gn * a.sbn + gk) : (gn + gk * a.sbk)] : 0.0; \
+    }                                                                                        \
+  }
+#define F64_SSTORE(buf)                                  \
+  {                                                      \
+    _Pragma("unroll") for (int e = 0; e < EA; ++e) {     \
+      const int idx = tid + e * 256;                     \
+      const int mm = AK ? idx / BK : idx % BM;           \
+      const int kk = AK ? idx % BK : idx / BM;           \
+      As[buf][kk][mm] = ra[e];                           \
+    }                                                    \
+    _Pragma("unroll") for (int e = 0; e < EB; ++e) {     \
+      const int idx = tid + e * 256;                     \
+      const int nn = BKC ? idx / BK : idx % BN;          \
+      const int kk = BKC ? idx % BK : idx / BN;          \
+      Bs[buf][kk][nn] = rb[e];                           \
+    }                                                    \
+  }
+
   const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   if (nk > 0) {
-    gload(kbeg);
-    sstore(0);
+    F64_GLOAD(kbeg);
+    F64_SSTORE(0);
   }
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = (int)(kt & 1);
-    if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+    if (kt + 1 < nk) F64_GLOAD(kbeg + (kt + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       double af[TM], bf[TN];
@@ -163,9 +164,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs a) {
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+    if (kt + 1 < nk) F64_SSTORE(cur ^ 1);
     __syncthreads();
   }
+#undef F64_GLOAD
+#undef F64_SSTORE
 
   // v_mfma_f64_16x16x4f64 result layout: element (i, j) of the 16 x 16 tile is
   // register i / 4 of lane j + 16 * (i % 4).
@@ -177,163 +180,220 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs a) {
       for (int r = 0; r < 4; ++r) {
         const int64_t gm = m0 + wm * WM + i * 16 + 4 * r + (lane >> 4);
         const int64_t gn = n0 + wn * WN + j * 16 + (lane & 15);
-        if (gm < a.M && gn < a.N) store_out<double>(a, b, split, gm, gn, acc[i][j][r]);
+        if (gm < a.M && gn < a.N) store_out<double>(a, tc, gm, gn, acc[i][j][r]);
       }
 }
 
 // ------------------------------------------------------------------ BF16 ----
-union Pack8 {
-  uint4 u;
-  bf16_t h[8];
+constexpr int BBK = 64;         // K slice
+constexpr int BLDK = BBK + 8;   // padded LDS row (bf16 elements)
+
+// 8 bf16 at p[0], p[step], ... with the elements at index >= count set to 0.
+__device__ __forceinline__ uint4 gather8(const bf16_t* p, int64_t step, int64_t count) {
+  uint32_t w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t lo = (2 * q < count) ? (uint32_t)p[(2 * q) * step] : 0u;
+    const uint32_t hi = (2 * q + 1 < count) ? (uint32_t)p[(2 * q + 1) * step] : 0u;
+    w[q] = lo | (hi << 16);
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// One operand tile (ROWS x BBK) of a BF16 GEMM: global -> registers -> LDS
+// (LDS layout [row][k] with padded rows).  KC: the operand's unit stride is
+// along k; otherwise along the row index and the tile is transposed on its
+// way into LDS.
+template <int ROWS, bool KC>
+struct BfTile {
+  static constexpr int C = ROWS * BBK / 8 / 256;
+  __device__ __forceinline__ static void load(uint4 (&r)[C], const bf16_t* X, int64_t s_row,
+                                              int64_t s_k, int64_t row0, int64_t nrows, int64_t k0,
+                                              int64_t kend, bool vec, int tid) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const int c = tid + e * 256;
+      if (KC) {
+        const int row = c / (BBK / 8), kk = (c % (BBK / 8)) * 8;
+        const int64_t g = row0 + row, gk = k0 + kk;
+        const bf16_t* p = X + g * s_row + gk;
+        if (vec && g < nrows && gk + 8 <= kend) r[e] = *(const uint4*)p;
+        else r[e] = gather8(p, 1, g < nrows ? kend - gk : 0);
+      } else {
+        const int kk = c / (ROWS / 8), row = (c % (ROWS / 8)) * 8;
+        const int64_t g = row0 + row, gk = k0 + kk;
+        const bf16_t* p = X + gk * s_k + g;
+        if (vec && gk < kend && g + 8 <= nrows) r[e] = *(const uint4*)p;
+        else r[e] = gather8(p, 1, gk < kend ? nrows - g : 0);
+      }
+    }
+  }
+  __device__ __forceinline__ static void store(const uint4 (&r)[C], bf16_t* S, int tid) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const int c = tid + e * 256;
+      if (KC) {
+        const int row = c / (BBK / 8), kk = (c % (BBK / 8)) * 8;
+        *(uint4*)&S[row * BLDK + kk] = r[e];
+      } else {
+        const int kk = c / (ROWS / 8), row = (c % (ROWS / 8)) * 8;
+        const uint32_t w[4] = {r[e].x, r[e].y, r[e].z, r[e].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          S[(row + 2 * q) * BLDK + kk] = (bf16_t)(w[q] & 0xffffu);
+          S[(row + 2 * q + 1) * BLDK + kk] = (bf16_t)(w[q] >> 16);
+        }
+      }
+    }
+  }
 };
 
+template <typename OutT>
+__device__ __forceinline__ OutT to_out(float v);
+template <> __device__ __forceinline__ float to_out<float>(float v) { return v; }
+template <> __device__ __forceinline__ bf16_t to_out<bf16_t>(float v) { return f32_to_bf16(v); }
+template <> __device__ __forceinline__ double to_out<double>(float v) { return (double)v; }
+
 template <int BM, int BN, bool AK, bool BKC, typename OutT>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(KArgs a) {
-  constexpr int BK = 64, LDK = BK + 8;
+__global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(const KArgs a) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int CA = BM * BK / 8 / 256, CB = BN * BK / 8 / 256;
-  __shared__ __attribute__((aligned(16))) bf16_t As[2][BM * LDK];
-  __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN * LDK];
+  constexpr int AS = BM * BLDK, BS = BN * BLDK;  // bf16 elements per buffer
+  // staged epilogue: OutT (or float for split-K partials) tile with padded rows
+  constexpr bool STAGE = sizeof(OutT) <= 4;
+  constexpr int ESZ = sizeof(OutT) <= 4 ? (int)sizeof(OutT) : 4;
+  constexpr int LDC = BN + 16 / ESZ;
+  constexpr int SMEM_AB = 2 * (AS + BS) * 2;
+  constexpr int SMEM_C = STAGE ? BM * LDC * ESZ : 0;
+  constexpr int SMEM = SMEM_AB > SMEM_C ? SMEM_AB : SMEM_C;
+  __shared__ __attribute__((aligned(16))) char smem[SMEM];
+  bf16_t* As = (bf16_t*)smem;             // [2][AS]
+  bf16_t* Bs = (bf16_t*)smem + 2 * AS;    // [2][BS]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
-  int64_t b, tm, tn;
-  int split;
-  tile_coords(lid, a, b, split, tm, tn);
-  const int64_t m0 = tm * BM, n0 = tn * BN;
-  const int64_t kbeg = (int64_t)split * a.kchunk;
+  const Coords tc = tile_coords(xcd_remap(blockIdx.x, gridDim.x), a);
+  const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
+  const int64_t kbeg = (int64_t)tc.split * a.kchunk;
   const int64_t kend = min(a.K, kbeg + a.kchunk);
-  const bf16_t* A = (const bf16_t*)a.A + b * a.sab;
-  const bf16_t* B = (const bf16_t*)a.B + b * a.sbb;
+  const bf16_t* A = (const bf16_t*)a.A + tc.b * a.sab;
+  const bf16_t* B = (const bf16_t*)a.B + tc.b * a.sbb;
   const bool vec = a.vec_ok != 0;
+  using TA = BfTile<BM, AK>;
+  using TB = BfTile<BN, BKC>;
+  const int64_t sa_row = AK ? a.sam : 1, sa_k = AK ? 1 : a.sak;
+  const int64_t sb_row = BKC ? a.sbn : 1, sb_k = BKC ? 1 : a.sbk;
 
-  Pack8 ra[CA], rb[CB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int e = 0; e < CA; ++e) {
-      const int c = tid + e * 256;
-      if (AK) {
-        const int mm = c / (BK / 8), kk = (c % (BK / 8)) * 8;
-        const int64_t gm = m0 + mm, gk = k0 + kk;
-        if (vec && gm < a.M && gk + 8 <= kend) {
-          ra[e].u = *(const uint4*)(A + gm * a.sam + gk);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 8; ++i)
-            ra[e].h[i] = (gm < a.M && gk + i < kend) ? A[gm * a.sam + gk + i] : (bf16_t)0;
-        }
-      } else {
-        const int kk = c / (BM / 8), mm = (c % (BM / 8)) * 8;
-        const int64_t gm = m0 + mm, gk = k0 + kk;
-        if (vec && gk < kend && gm + 8 <= a.M) {
-          ra[e].u = *(const uint4*)(A + gk * a.sak + gm);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 8; ++i)
-            ra[e].h[i] = (gk < kend && gm + i < a.M) ? A[gk * a.sak + gm + i] : (bf16_t)0;
-        }
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < CB; ++e) {
-      const int c = tid + e * 256;
-      if (BKC) {
-        const int nn = c / (BK / 8), kk = (c % (BK / 8)) * 8;
-        const int64_t gn = n0 + nn, gk = k0 + kk;
-        if (vec && gn < a.N && gk + 8 <= kend) {
-          rb[e].u = *(const uint4*)(B + gn * a.sbn + gk);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 8; ++i)
-            rb[e].h[i] = (gn < a.N && gk + i < kend) ? B[gn * a.sbn + gk + i] : (bf16_t)0;
-        }
-      } else {
-        const int kk = c / (BN / 8), nn = (c % (BN / 8)) * 8;
-        const int64_t gn = n0 + nn, gk = k0 + kk;
-        if (vec && gk < kend && gn + 8 <= a.N) {
-          rb[e].u = *(const uint4*)(B + gk * a.sbk + gn);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 8; ++i)
-            rb[e].h[i] = (gk < kend && gn + i < a.N) ? B[gk * a.sbk + gn + i] : (bf16_t)0;
-        }
-      }
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < CA; ++e) {
-      const int c = tid + e * 256;
-      if (AK) {
-        const int mm = c / (BK / 8), kk = (c % (BK / 8)) * 8;
-        *(uint4*)&As[buf][mm * LDK + kk] = ra[e].u;
-      } else {
-        const int kk = c / (BM / 8), mm = (c % (BM / 8)) * 8;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) As[buf][(mm + i) * LDK + kk] = ra[e].h[i];
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < CB; ++e) {
-      const int c = tid + e * 256;
-      if (BKC) {
-        const int nn = c / (BK / 8), kk = (c % (BK / 8)) * 8;
-        *(uint4*)&Bs[buf][nn * LDK + kk] = rb[e].u;
-      } else {
-        const int kk = c / (BN / 8), nn = (c % (BN / 8)) * 8;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) Bs[buf][(nn + i) * LDK + kk] = rb[e].h[i];
-      }
-    }
-  };
-
+  uint4 ra[TA::C], rb[TB::C];
   f4_t acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-  const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  const int64_t nk = kend > kbeg ? (kend - kbeg + BBK - 1) / BBK : 0;
   if (nk > 0) {
-    gload(kbeg);
-    sstore(0);
+    TA::load(ra, A, sa_row, sa_k, m0, a.M, kbeg, kend, vec, tid);
+    TB::load(rb, B, sb_row, sb_k, n0, a.N, kbeg, kend, vec, tid);
+    TA::store(ra, As, tid);
+    TB::store(rb, Bs, tid);
   }
   __syncthreads();
   const int fr = lane & 15, fk = 8 * (lane >> 4);
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = (int)(kt & 1);
-    if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+    const bf16_t* Ac = As + cur * AS;
+    const bf16_t* Bc = Bs + cur * BS;
+    if (kt + 1 < nk) {
+      const int64_t k1 = kbeg + (kt + 1) * BBK;
+      TA::load(ra, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
+      TB::load(rb, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
+    }
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += 32) {
+    for (int ks = 0; ks < BBK; ks += 32) {
       bf16x8_t af[TM], bfr[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
-        af[i] = *(const bf16x8_t*)&As[cur][(wm * WM + i * 16 + fr) * LDK + ks + fk];
+        af[i] = *(const bf16x8_t*)&Ac[(wm * WM + i * 16 + fr) * BLDK + ks + fk];
 #pragma unroll
       for (int j = 0; j < TN; ++j)
-        bfr[j] = *(const bf16x8_t*)&Bs[cur][(wn * WN + j * 16 + fr) * LDK + ks + fk];
+        bfr[j] = *(const bf16x8_t*)&Bc[(wn * WN + j * 16 + fr) * BLDK + ks + fk];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+    if (kt + 1 < nk) {
+      TA::store(ra, As + (cur ^ 1) * AS, tid);
+      TB::store(rb, Bs + (cur ^ 1) * BS, tid);
+    }
     __syncthreads();
   }
 
+  // v_mfma_f32_16x16x32_bf16 result layout: element (i, j) of the 16 x 16 tile
+  // is register i % 4 of lane j + 16 (i / 4).
+  if constexpr (STAGE) {
+    // Stage the tile through LDS (the K-loop buffers are free after the last
+    // barrier) and write whole 16-byte row chunks.
+    using ST = typename std::conditional<sizeof(OutT) <= 4, OutT, float>::type;
+    const bool part = a.splits > 1;
+    ST* Cs = (ST*)smem;
+    const float alpha = part ? 1.0f : (float)a.alpha;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gm = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
-        const int64_t gn = n0 + wn * WN + j * 16 + (lane & 15);
-        if (gm < a.M && gn < a.N) store_out<OutT>(a, b, split, gm, gn, (double)acc[i][j][r]);
+        for (int r = 0; r < 4; ++r) {
+          const int lm = wm * WM + i * 16 + 4 * (lane >> 4) + r;
+          const int ln = wn * WN + j * 16 + (lane & 15);
+          if (part) ((float*)smem)[lm * (BN + 4) + ln] = acc[i][j][r];
+          else Cs[lm * LDC + ln] = to_out<ST>(alpha * acc[i][j][r]);
+        }
+    __syncthreads();
+    if (part) {
+      constexpr int EPC = 4, CPR = BN / EPC;
+      float* dst = (float*)a.partial + ((int64_t)tc.split * a.batch + tc.b) * a.M * a.N;
+      const float* src = (const float*)smem;
+      for (int c = tid; c < BM * CPR; c += 256) {
+        const int row = c / CPR, col = (c % CPR) * EPC;
+        const int64_t gm = m0 + row, gn = n0 + col;
+        if (gm >= a.M) continue;
+        if (a.cvec_ok && gn + EPC <= a.N) {
+          *(uint4*)(dst + gm * a.N + gn) = *(const uint4*)(src + row * (BN + 4) + col);
+        } else {
+          for (int q = 0; q < EPC; ++q)
+            if (gn + q < a.N) dst[gm * a.N + gn + q] = src[row * (BN + 4) + col + q];
+        }
       }
+    } else {
+      constexpr int EPC = 16 / (int)sizeof(ST), CPR = BN / EPC;
+      ST* dst = (ST*)a.C + tc.b * a.scb;
+      for (int c = tid; c < BM * CPR; c += 256) {
+        const int row = c / CPR, col = (c % CPR) * EPC;
+        const int64_t gm = m0 + row, gn = n0 + col;
+        if (gm >= a.M) continue;
+        if (a.cvec_ok && gn + EPC <= a.N) {
+          *(uint4*)(dst + gm * a.scm + gn) = *(const uint4*)(Cs + row * LDC + col);
+        } else {
+          for (int q = 0; q < EPC; ++q)
+            if (gn + q < a.N) dst[gm * a.scm + gn + q] = Cs[row * LDC + col + q];
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gm = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+          const int64_t gn = n0 + wn * WN + j * 16 + (lane & 15);
+          if (gm < a.M && gn < a.N) store_out<OutT>(a, tc, gm, gn, (double)acc[i][j][r]);
+        }
+  }
 }
 
 // Sums the split-K partials in split order and applies alpha / beta.
@@ -373,6 +433,7 @@ KArgs make_args(const Gemm& g, int BM, int BN, int BK) {
   a.tiles_m = (g.M + BM - 1) / BM;
   a.tiles_n = (g.N + BN - 1) / BN;
   a.vec_ok = 0;
+  a.cvec_ok = 0;
   return a;
 }
 
@@ -447,6 +508,12 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
   const int64_t sa_row = ak ? g.sam : g.sak, sb_row = bk ? g.sbn : g.sbk;
   a.vec_ok = (al(g.A) && al(g.B) && sa_row % 8 == 0 && sb_row % 8 == 0 && g.sab % 8 == 0 &&
               g.sbb % 8 == 0) ? 1 : 0;
+  if (a.splits > 1) {
+    a.cvec_ok = (al(g.partial) && g.N % 4 == 0) ? 1 : 0;
+  } else {
+    const int64_t epc = g.ctype == DType::BF16 ? 8 : (g.ctype == DType::F32 ? 4 : 2);
+    a.cvec_ok = (al(g.C) && g.scm % epc == 0 && g.scb % epc == 0) ? 1 : 0;
+  }
   const int64_t blocks = a.tiles_m * a.tiles_n * a.batch * a.splits;
   if (blocks == 0) return;
   if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_bf16: grid too large");

@@ -1,25 +1,27 @@
-// FP64 Cholesky factorisation and SPD solve for the ALS normal equations
-// (W F^T = M^T, Section "Optimizing the CP-PPL tensor-network": W is the
-// Hadamard product of the other factors' Grams and is solved by Cholesky).
+// FP64 inverse of the ALS normal-equation matrix W (Section "Optimizing the
+// CP-PPL tensor-network": W is the Hadamard product of the other factors'
+// Grams; the update is F = M W^{-1}).
+//
+// W is inverted by the block sweep (Gauss-Jordan) operator: sweeping every
+// 64 x 64 pivot block of a symmetric positive-definite matrix once turns it
+// into -W^{-1}.  Each block step is one launch in which every work-group
+// inverts the pivot block itself (no inter-group waits) and writes its own
+// output tile; two buffers alternate so no launch reads what it writes.  The
+// factor update is then one GEMM, F^T = W^{-1} M^T, and the inversion only
+// needs the Grams, so it can run before the MTTKRP it is applied to is ready.
 #pragma once
 
 #include "common.h"
 
 namespace cpppl {
 
-constexpr int CHOL_NB = 64;
+constexpr int INV_NB = 64;
 
-// Lower Cholesky of the R x R row-major SPD matrix A.  The strictly-lower
-// off-diagonal blocks of L overwrite those of A; the factored 64 x 64 diagonal
-// blocks (padded with the identity) go to Dsave (diag_save_elems(R) doubles).
-// A pivot that is <= 0 or not finite sets status[0] = 1 and is replaced by 1
-// so that the factorisation stays finite.
-void cholesky(double* A, int64_t R, double* Dsave, int* status, hipStream_t s);
-int64_t diag_save_elems(int64_t R);
-
-// X (R x n, row-major) <- (L L^T)^{-1} X for the factor left by cholesky().
-void spd_solve(const double* A, const double* Dsave, int64_t R, double* X, int64_t n,
-               hipStream_t s);
+// -W^{-1} of the R x R row-major SPD matrix in bufA (overwritten), using bufB
+// as the second buffer; returns the buffer holding the result.  A pivot that
+// is <= 0 or not finite sets status[0] = 1 and is replaced by 1 so that the
+// result stays finite.
+double* spd_inverse_neg(double* bufA, double* bufB, int64_t R, int* status, hipStream_t s);
 
 // A_ii += delta * trace(A) / R.
 void add_ridge(double* A, int64_t R, double delta, hipStream_t s);

@@ -1,117 +1,187 @@
-// Blocked right-looking Cholesky and the two triangular solves of the ALS
-// normal equations, FP64.
+// Block sweep-operator inverse of the ALS normal-equation matrix, FP64.
 //
-// Per 64-wide block column: one kernel factors the diagonal block in LDS
-// (every work-group redundantly, so no inter-group wait is needed) and the
-// work-groups then solve the panel rows below it, one row per lane, against
-// the factored block; the trailing update is an FP64 matrix-core GEMM.  The
-// solves walk block rows the same way: a small kernel solves one block row
-// (one right-hand-side column per lane) and a GEMM updates the rest.
-// Partial blocks are padded with the identity.
+// Sweeping pivot block k of a symmetric matrix A (D = A_kk^{-1}):
+//   A_ij <- A_ij - A_ik D A_kj   (i, j != k)
+//   A_ik <- A_ik D,  A_kj <- D A_kj,  A_kk <- -D
+// After every block has been swept once, A holds -A^{-1}.  One launch per
+// block step; work-group (I, J) re-inverts the 64 x 64 pivot block in LDS
+// (Gauss-Jordan, no pivoting: the pivots of an SPD matrix are positive) and
+// then writes output tile (I, J) from the input buffer into the other buffer.
+// The 64 x 64 products use 4 x 4 register micro-tiles per lane.
 #include "linalg.h"
 
-#include "gemm.h"
+#include <utility>
 
 namespace cpppl {
 
 namespace {
 
-constexpr int NB = CHOL_NB;
+constexpr int NB = INV_NB;
+constexpr int LD = NB + 1;
 
-// Loads the (padded) diagonal block at k0 into D and factors it in place.
-// Returns false (block-uniformly) if a pivot was bad.
-__device__ inline bool factor_diag(const double* A, int64_t R, int64_t k0, int nb,
-                                   double (*D)[NB + 1]) {
+// In-place Gauss-Jordan inverse of the NB x NB block P (row stride LD) in LDS.
+// Lane t keeps the 4 x 4 block (rows 4 (t / 16) + r, columns 4 (t % 16) + c) in
+// registers; at pivot k the owners of row k and column k publish them through
+// LDS vectors that alternate between two buffers, so one barrier per pivot
+// suffices.
+__device__ bool gj_inverse(double* P, double (*sr)[NB], double (*sc)[NB]) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int i = e / NB, j = e % NB;
-    double v;
-    if (i < nb && j < nb) v = (j <= i) ? A[(k0 + i) * R + k0 + j] : 0.0;
-    else v = (i == j) ? 1.0 : 0.0;
-    D[i][j] = v;
+  const int i0 = 4 * (tid >> 4), j0 = 4 * (tid & 15);
+  double a[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[r][c] = P[(i0 + r) * LD + j0 + c];
+  bool ok = true;
+  for (int k = 0; k < NB; ++k) {
+    const int b = k & 1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (i0 + r == k) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sr[b][j0 + c] = a[r][c];
+      }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (j0 + c == k) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sc[b][i0 + r] = a[r][c];
+      }
+    __syncthreads();
+    double p = sr[b][k];
+    const bool bad = !(p > 0.0) || !isfinite(p);
+    ok = ok && !bad;
+    if (bad) p = 1.0;
+    const double inv = 1.0 / p;
+    double rowk[4], colk[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rowk[c] = sr[b][j0 + c] * inv;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) colk[r] = sc[b][i0 + r];
+    // branch-free update: every lane computes all four cases and selects
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool ri = (i0 + r == k);
+      const double colv = -colk[r] * inv;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bool cj = (j0 + c == k);
+        const double gen = a[r][c] - colk[r] * rowk[c];
+        const double on_row = cj ? inv : rowk[c];
+        const double off_row = cj ? colv : gen;
+        a[r][c] = ri ? on_row : off_row;
+      }
+    }
   }
   __syncthreads();
-  bool ok = true;
-  for (int j = 0; j < NB; ++j) {
-    const double d = D[j][j];
-    const bool bad = !(d > 0.0) || !isfinite(d);
-    ok = ok && !bad;
-    const double sd = bad ? 1.0 : sqrt(d);
-    __syncthreads();
-    if (tid == 0) D[j][j] = sd;
-    const double inv = 1.0 / sd;
-    for (int i = j + 1 + tid; i < NB; i += blockDim.x) D[i][j] *= inv;
-    __syncthreads();
-    const int m = NB - j - 1;
-    for (int e = tid; e < m * m; e += blockDim.x) {
-      const int i = j + 1 + e / m, l = j + 1 + e % m;
-      if (l <= i) D[i][l] -= D[i][j] * D[l][j];
-    }
-    __syncthreads();
-  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) P[(i0 + r) * LD + j0 + c] = a[r][c];
+  __syncthreads();
   return ok;
 }
 
-// Block 0 saves the factored (padded) diagonal block to Dsave; blocks b >= 1
-// solve panel rows k0 + nb + (b-1)*SUB + lane:  x L_kk^T = a.  The diagonal
-// block of A is only read here, so no block waits on another.  Each lane keeps
-// its row in its own LDS column Xs[.][lane] (conflict-free, no spills).
-constexpr int SUB = 128;
-
-__global__ __launch_bounds__(SUB) void chol_panel_kernel(double* A, int64_t R, int64_t k0,
-                                                         double* Dsave, int* status) {
-  __shared__ double D[NB][NB + 1];
-  __shared__ double Xs[NB][SUB];
-  const int nb = (int)min((int64_t)NB, R - k0);
-  const bool ok = factor_diag(A, R, k0, nb, D);
-  const int tid = threadIdx.x;
-  if (blockIdx.x == 0) {
-    if (!ok && tid == 0) status[0] = 1;
-    double* out = Dsave + (k0 / NB) * NB * NB;
-    for (int e = tid; e < NB * NB; e += blockDim.x) out[e] = D[e / NB][e % NB];
-    return;
+// acc += X[rows of this lane][:] . Y[:][cols of this lane]; lane t owns rows
+// 4 (t / 16) + r and columns (t % 16) + 16 c.
+__device__ inline void mm64(const double* X, const double* Y, double acc[4][4]) {
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  for (int l = 0; l < NB; ++l) {
+    double a[4], b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = X[(4 * ti + r) * LD + l];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) b[c] = Y[l * LD + tj + 16 * c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
   }
-  const int64_t row = k0 + nb + (int64_t)(blockIdx.x - 1) * SUB + tid;
-  if (row >= R) return;
-  double* a = A + row * R + k0;
-  for (int j = 0; j < NB; ++j) Xs[j][tid] = (j < nb) ? a[j] : 0.0;
-  for (int j = 0; j < nb; ++j) {
-    const double xj = Xs[j][tid] / D[j][j];
-    Xs[j][tid] = xj;
-    for (int l = j + 1; l < nb; ++l) Xs[l][tid] -= xj * D[l][j];
-  }
-  for (int j = 0; j < nb; ++j) a[j] = Xs[j][tid];
 }
 
-// Forward (lower) or backward (transposed lower) substitution on block row k0
-// of X (R x n), one right-hand-side column per lane, kept in Xs[.][lane].
-template <bool FORWARD>
-__global__ __launch_bounds__(SUB) void trsm_diag_kernel(const double* Dsave, int64_t R, int64_t k0,
-                                                        double* X, int64_t n) {
-  __shared__ double D[NB][NB + 1];
-  __shared__ double Xs[NB][SUB];
-  const int nb = (int)min((int64_t)NB, R - k0);
-  const double* src = Dsave + (k0 / NB) * NB * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) D[e / NB][e % NB] = src[e];
-  __syncthreads();
-  const int tid = threadIdx.x;
-  const int64_t c = (int64_t)blockIdx.x * SUB + tid;
-  if (c >= n) return;
-  for (int i = 0; i < nb; ++i) Xs[i][tid] = X[(k0 + i) * n + c];
-  if (FORWARD) {
-    for (int j = 0; j < nb; ++j) {
-      const double xj = Xs[j][tid] / D[j][j];
-      Xs[j][tid] = xj;
-      for (int i = j + 1; i < nb; ++i) Xs[i][tid] -= D[i][j] * xj;
-    }
-  } else {
-    for (int j = nb - 1; j >= 0; --j) {
-      const double xj = Xs[j][tid] / D[j][j];
-      Xs[j][tid] = xj;
-      for (int i = 0; i < j; ++i) Xs[i][tid] -= D[j][i] * xj;
-    }
+__device__ inline void load_tile(const double* A, int64_t R, int64_t r0, int64_t c0, int nr,
+                                 int nc, double* T) {
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    T[i * LD + j] = (i < nr && j < nc) ? A[(r0 + i) * R + c0 + j] : 0.0;
   }
-  for (int i = 0; i < nb; ++i) X[(k0 + i) * n + c] = Xs[i][tid];
+}
+
+__global__ __launch_bounds__(256) void sweep_kernel(const double* __restrict__ A,
+                                                    double* __restrict__ O, int64_t R, int64_t kb,
+                                                    int* status) {
+  __shared__ double D[NB * LD];
+  __shared__ double T1[NB * LD];
+  __shared__ double T2[NB * LD];
+  __shared__ double sr[2][NB], sc[2][NB];
+  const int tid = threadIdx.x;
+  const int64_t T = (R + NB - 1) / NB;
+  const int64_t I = blockIdx.x / T, J = blockIdx.x % T;
+  const int64_t k0 = kb * NB, i0 = I * NB, j0 = J * NB;
+  const int nk = (int)min((int64_t)NB, R - k0);
+  const int ni = (int)min((int64_t)NB, R - i0);
+  const int nj = (int)min((int64_t)NB, R - j0);
+
+  // pivot block, padded with the identity
+  for (int e = tid; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    D[i * LD + j] = (i < nk && j < nk) ? A[(k0 + i) * R + k0 + j] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const bool ok = gj_inverse(D, sr, sc);
+  if (!ok && blockIdx.x == 0 && tid == 0) status[0] = 1;
+
+  const int ti = tid >> 4, tj = tid & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+
+  if (I == kb && J == kb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = -D[(4 * ti + r) * LD + tj + 16 * c];
+  } else if (J == kb) {  // A_Ik D
+    load_tile(A, R, i0, k0, ni, nk, T1);
+    __syncthreads();
+    mm64(T1, D, acc);
+  } else if (I == kb) {  // D A_kJ
+    load_tile(A, R, k0, j0, nk, nj, T2);
+    __syncthreads();
+    mm64(D, T2, acc);
+  } else {  // A_IJ - (A_Ik D) A_kJ
+    load_tile(A, R, i0, k0, ni, nk, T1);
+    load_tile(A, R, k0, j0, nk, nj, T2);
+    __syncthreads();
+    mm64(T1, D, acc);
+    __syncthreads();  // every lane has read T1 before it is overwritten with C
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) T1[(4 * ti + r) * LD + tj + 16 * c] = acc[r][c];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    mm64(T1, T2, acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int i = 4 * ti + r, j = tj + 16 * c;
+        if (i < ni && j < nj) acc[r][c] = A[(i0 + i) * R + j0 + j] - acc[r][c];
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = 4 * ti + r, j = tj + 16 * c;
+      if (i < ni && j < nj) O[(i0 + i) * R + j0 + j] = acc[r][c];
+    }
 }
 
 __global__ __launch_bounds__(256) void ridge_kernel(double* A, int64_t R, double delta) {
@@ -130,62 +200,17 @@ __global__ __launch_bounds__(256) void ridge_kernel(double* A, int64_t R, double
 
 }  // namespace
 
-int64_t diag_save_elems(int64_t R) { return ((R + NB - 1) / NB) * NB * NB; }
-
-void cholesky(double* A, int64_t R, double* Dsave, int* status, hipStream_t s) {
-  for (int64_t k0 = 0; k0 < R; k0 += NB) {
-    const int64_t nb = std::min<int64_t>(NB, R - k0);
-    const int64_t below = R - k0 - nb;
-    const unsigned blocks = 1 + (unsigned)((below + SUB - 1) / SUB);
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(blocks), dim3(SUB), 0, s, A, R, k0, Dsave, status);
-    CPPPL_LAUNCH_CHECK("chol_panel");
-    if (below > 0) {
-      // A22 -= L21 L21^T  (full square; only the lower part is used later)
-      Gemm g;
-      g.M = below; g.N = below; g.K = nb;
-      g.A = A + (k0 + nb) * R + k0; g.sam = R; g.sak = 1;
-      g.B = A + (k0 + nb) * R + k0; g.sbn = R; g.sbk = 1;
-      g.C = A + (k0 + nb) * R + k0 + nb; g.scm = R;
-      g.ctype = DType::F64; g.alpha = -1.0; g.beta = 1.0;
-      gemm_f64(g, s);
-    }
+double* spd_inverse_neg(double* bufA, double* bufB, int64_t R, int* status, hipStream_t s) {
+  const int64_t T = (R + NB - 1) / NB;
+  double* in = bufA;
+  double* out = bufB;
+  for (int64_t kb = 0; kb < T; ++kb) {
+    hipLaunchKernelGGL(sweep_kernel, dim3((unsigned)(T * T)), dim3(256), 0, s, in, out, R, kb,
+                       status);
+    CPPPL_LAUNCH_CHECK("sweep");
+    std::swap(in, out);
   }
-}
-
-void spd_solve(const double* L, const double* Dsave, int64_t R, double* X, int64_t n,
-               hipStream_t s) {
-  const unsigned cb = (unsigned)((n + SUB - 1) / SUB);
-  for (int64_t k0 = 0; k0 < R; k0 += NB) {
-    const int64_t nb = std::min<int64_t>(NB, R - k0);
-    hipLaunchKernelGGL(trsm_diag_kernel<true>, dim3(cb), dim3(SUB), 0, s, Dsave, R, k0, X, n);
-    CPPPL_LAUNCH_CHECK("trsm_fwd");
-    const int64_t below = R - k0 - nb;
-    if (below > 0) {
-      Gemm g;  // X[k0+nb:, :] -= L[k0+nb:, k0:k0+nb] X[k0:k0+nb, :]
-      g.M = below; g.N = n; g.K = nb;
-      g.A = L + (k0 + nb) * R + k0; g.sam = R; g.sak = 1;
-      g.B = X + k0 * n; g.sbk = n; g.sbn = 1;
-      g.C = X + (k0 + nb) * n; g.scm = n;
-      g.ctype = DType::F64; g.alpha = -1.0; g.beta = 1.0;
-      gemm_f64(g, s);
-    }
-  }
-  const int64_t nblk = (R + NB - 1) / NB;
-  for (int64_t kb = nblk - 1; kb >= 0; --kb) {
-    const int64_t k0 = kb * NB;
-    const int64_t nb = std::min<int64_t>(NB, R - k0);
-    hipLaunchKernelGGL(trsm_diag_kernel<false>, dim3(cb), dim3(SUB), 0, s, Dsave, R, k0, X, n);
-    CPPPL_LAUNCH_CHECK("trsm_bwd");
-    if (k0 > 0) {
-      Gemm g;  // X[:k0, :] -= L[k0:k0+nb, :k0]^T X[k0:k0+nb, :]
-      g.M = k0; g.N = n; g.K = nb;
-      g.A = L + k0 * R; g.sam = 1; g.sak = R;
-      g.B = X + k0 * n; g.sbk = n; g.sbn = 1;
-      g.C = X; g.scm = n;
-      g.ctype = DType::F64; g.alpha = -1.0; g.beta = 1.0;
-      gemm_f64(g, s);
-    }
-  }
+  return in;
 }
 
 void add_ridge(double* A, int64_t R, double delta, hipStream_t s) {

@@ -37,12 +37,17 @@ CPPPL_API cpppl_status cpppl_test_gemm(int in_dtype, int64_t M, int64_t N, int64
   return CPPPL_OK;
 }
 
-CPPPL_API cpppl_status cpppl_test_spd_solve(double* W, int64_t R, double* X, int64_t n,
-                                            double* dsave, int* status, void* stream) {
+CPPPL_API cpppl_status cpppl_test_spd_solve(double* W, int64_t R, const double* X, double* Y,
+                                            int64_t n, double* work, int* status, void* stream) {
   try {
     hipStream_t s = (hipStream_t)stream;
-    cholesky(W, R, dsave, status, s);
-    spd_solve(W, dsave, R, X, n, s);
+    double* inv = spd_inverse_neg(W, work, R, status, s);
+    Gemm g;
+    g.M = R; g.N = n; g.K = R;
+    g.A = inv; g.sam = R; g.sak = 1;
+    g.B = X; g.sbk = n; g.sbn = 1;
+    g.C = Y; g.scm = n; g.ctype = DType::F64; g.alpha = -1.0;
+    gemm_f64(g, s);
     if (hipStreamSynchronize(s) != hipSuccess) return CPPPL_E_HIP;
   } catch (const HipError& e) {
     fprintf(stderr, "cpppl_test_spd_solve: %s: %s\n", e.where, hipGetErrorString(e.err));

@@ -122,6 +122,13 @@ def test_r_two_routes_and_blocking():
     np.testing.assert_allclose(rows, r1.reshape(9, 5, 5)[2:7], atol=1e-13 * np.abs(r2).max())
 
 
+def test_r_pairs_route_matches():
+    b, t, _ = _rand_problem(4, 6, 5, 2, 13)
+    r = oracle.form_r(t, b)
+    np.testing.assert_allclose(oracle.form_r_pairs(t, b, 3), r[:3, :3],
+                               atol=1e-13 * np.abs(r).max())
+
+
 def test_r_pair_symmetry_with_symmetric_inputs():
     cfg = synth.CONFIGS["C1"]
     inp = synth.make_inputs(cfg)
