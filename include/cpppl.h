@@ -166,9 +166,12 @@ CPPPL_API cpppl_status cpppl_energy(cpppl_ctx* ctx, double* e_cp);
 /* ---- learned warm start (previous converged factors -> next warm start) ------------ */
 
 /* Multi-layer perceptron applied per rank column: in_dim -> hidden (x n_hidden,
- * ReLU) -> out_dim, FP32, weights initialised U(-1/sqrt(fan_in), 1/sqrt(fan_in))
- * from a counter-based generator keyed by `seed`.  `capacity` = rows of
- * training pairs it can hold. */
+ * ReLU) -> out_dim, FP32.  Hidden weights start U(-1/sqrt(fan_in), 1/sqrt(fan_in))
+ * from a counter-based generator (SplitMix64) keyed by `seed`, biases and the
+ * last layer at zero (an untrained network predicts no correction).
+ * `capacity` = rows of training pairs it can hold.  The network owns its
+ * device memory (hipMalloc on `device`); its calls use the default stream and
+ * return after the work is done. */
 CPPPL_API cpppl_status cpppl_mlp_create(int in_dim, int hidden, int n_hidden, int out_dim,
                                         int64_t capacity, uint64_t seed, int device,
                                         cpppl_mlp** out);
@@ -187,6 +190,9 @@ CPPPL_API cpppl_status cpppl_mlp_grad(cpppl_mlp* mlp, const float* x, const floa
 CPPPL_API cpppl_status cpppl_mlp_add_rows(cpppl_mlp* mlp, const float* x, const float* y,
                                           int64_t n_rows, int on_device);
 CPPPL_API cpppl_status cpppl_mlp_clear_rows(cpppl_mlp* mlp);
+/* Number of stored training rows, and a copy of them (x: n x in_dim, y: n x out_dim). */
+CPPPL_API cpppl_status cpppl_mlp_num_rows(const cpppl_mlp* mlp, int64_t* n);
+CPPPL_API cpppl_status cpppl_mlp_get_rows(cpppl_mlp* mlp, float* x, float* y, int on_device);
 /* Adam (lr, 0.9, 0.999, 1e-8) over the stored rows in mini-batches of `batch`
  * rows (shuffled by a counter-based generator keyed by seed; batch <= 0: full
  * batch, no shuffle).  loss_hist (host, epochs entries) may be NULL. */

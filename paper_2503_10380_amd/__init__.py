@@ -100,6 +100,8 @@ def load_library(path: str = LIB_PATH):
         "cpppl_mlp_grad": (st, [_P, _P, _P, C.c_int64, _P, _P, C.c_int]),
         "cpppl_mlp_add_rows": (st, [_P, _P, _P, C.c_int64, C.c_int]),
         "cpppl_mlp_clear_rows": (st, [_P]),
+        "cpppl_mlp_num_rows": (st, [_P, C.POINTER(C.c_int64)]),
+        "cpppl_mlp_get_rows": (st, [_P, _P, _P, C.c_int]),
         "cpppl_mlp_train": (st, [_P, C.c_int, C.c_float, C.c_int64, C.c_uint64, _P]),
         "cpppl_mlp_save": (st, [_P, C.c_char_p]),
         "cpppl_mlp_load": (st, [_P, C.c_char_p]),
@@ -282,3 +284,117 @@ class Context:
         e = C.c_double()
         self._call("cpppl_energy", C.byref(e))
         return e.value
+
+    # ------------------------------------------------------------------ warm starts
+    @property
+    def ws_in_dim(self):
+        return self.lib.cpppl_ws_in_dim(C.byref(self.dims))
+
+    @property
+    def ws_out_dim(self):
+        return self.lib.cpppl_ws_out_dim(C.byref(self.dims))
+
+    def warm_start(self, dt, strategy=WS_PLAIN, mlp=None):
+        """t <- t + dt and warm-start the factors; returns the strategy chosen."""
+        keep = []
+        p, dev = self._arg(dt, (self.o, self.o, self.v, self.v), keep)
+        chosen = C.c_int(-1)
+        self._call("cpppl_warm_start", p, dev, int(strategy), mlp.h if mlp is not None else None,
+                   C.byref(chosen))
+        return chosen.value
+
+    def training_rows(self, mlp):
+        self._call("cpppl_ws_training_rows", mlp.h)
+
+
+class MLP:
+    """The per-rank-column warm-start network (FP32, trained on the GPU)."""
+
+    def __init__(self, in_dim, out_dim, hidden=256, n_hidden=2, capacity=0, seed=0, device=0):
+        _torch()
+        self.lib = load_library()
+        self.in_dim, self.out_dim = in_dim, out_dim
+        h = _P()
+        st = self.lib.cpppl_mlp_create(in_dim, hidden, n_hidden, out_dim, capacity, seed, device,
+                                       C.byref(h))
+        if st != 0:
+            raise CppplError(st, "cpppl_mlp_create failed")
+        self.h = h
+        n = C.c_int64()
+        self.lib.cpppl_mlp_num_params(self.h, C.byref(n))
+        self.nparams = n.value
+
+    def _check(self, st):
+        if st != 0:
+            raise CppplError(st, "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cpppl_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.empty(self.nparams, dtype=np.float32)
+        self._check(self.lib.cpppl_mlp_get_params(self.h, out.ctypes.data_as(_P), 0))
+        return out
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.nparams
+        self._check(self.lib.cpppl_mlp_set_params(self.h, a.ctypes.data_as(_P), 0))
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.empty((x.shape[0], self.out_dim), dtype=np.float32)
+        self._check(self.lib.cpppl_mlp_forward(self.h, x.ctypes.data_as(_P), x.shape[0],
+                                               y.ctypes.data_as(_P), 0))
+        return y
+
+    def grad(self, x, y):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        loss = C.c_float()
+        g = np.empty(self.nparams, dtype=np.float32)
+        self._check(self.lib.cpppl_mlp_grad(self.h, x.ctypes.data_as(_P), y.ctypes.data_as(_P),
+                                            x.shape[0], C.byref(loss), g.ctypes.data_as(_P), 0))
+        return loss.value, g
+
+    def add_rows(self, x, y):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        self._check(self.lib.cpppl_mlp_add_rows(self.h, x.ctypes.data_as(_P), y.ctypes.data_as(_P),
+                                                x.shape[0], 0))
+
+    def clear_rows(self):
+        self._check(self.lib.cpppl_mlp_clear_rows(self.h))
+
+    @property
+    def num_rows(self):
+        n = C.c_int64()
+        self._check(self.lib.cpppl_mlp_num_rows(self.h, C.byref(n)))
+        return n.value
+
+    def get_rows(self):
+        n = self.num_rows
+        x = np.empty((n, self.in_dim), dtype=np.float32)
+        y = np.empty((n, self.out_dim), dtype=np.float32)
+        self._check(self.lib.cpppl_mlp_get_rows(self.h, x.ctypes.data_as(_P), y.ctypes.data_as(_P), 0))
+        return x, y
+
+    def train(self, epochs, lr=1e-3, batch=0, seed=0):
+        hist = np.zeros(epochs, dtype=np.float32)
+        self._check(self.lib.cpppl_mlp_train(self.h, epochs, C.c_float(lr), batch, seed,
+                                             hist.ctypes.data_as(_P)))
+        return hist
+
+    def save(self, path):
+        self._check(self.lib.cpppl_mlp_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        self._check(self.lib.cpppl_mlp_load(self.h, str(path).encode()))

@@ -83,6 +83,11 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   p.MT = add((size_t)nmax * R * 8);
   p.stage = add((size_t)std::max<int64_t>(nmax * R, R * R) * 8);
   p.wsFeat = add((size_t)R * 2 * (2 * o + 2 * v) * 4);
+  p.wsOut = add((size_t)R * (2 * o + 2 * v) * 4);
+  p.dt64 = add(o2v2 * 8);
+  p.dt64T = add(o2v2 * 8);
+  p.dt16 = lp ? add(o2v2 * 2) : 0;
+  p.dt16T = lp ? add(o2v2 * 2) : 0;
   // intermediates, sized for FP64 and shared by the BF16 path
   const size_t tau_e = (size_t)(R * v * v), y_e = (size_t)(R * X * v);
   const size_t z_e = (size_t)(R * std::max(X, v) * v);  // Z, and G (R v^2) aliased on it
@@ -671,6 +676,43 @@ void ws_solve_no_update(cpppl_ctx* c, int mode, size_t out_off) {
   gemm_f64(g, c->stream);
 }
 void ws_init_after_factors(cpppl_ctx* c) { init_after_factors(c); }
+void ws_mttkrp_dt(cpppl_ctx* c, int mode) {
+  // the MTTKRP chain with dt in place of t (the PPL tensor is linear in t)
+  const DType dt = c->prec == CPPPL_BF16 ? DType::BF16 : DType::F64;
+  Path P = path_for(c, dt);
+  if (dt == DType::F64) {
+    P.T2 = c->at(c->plan.dt64);
+    P.T2T = c->at(c->plan.dt64T);
+  } else {
+    P.T2 = c->at(c->plan.dt16);
+    P.T2T = c->at(c->plan.dt16T);
+  }
+  mttkrp_into_MT(c, P, mode);
+}
+void ws_load_dt(cpppl_ctx* c, const double* dt, int on_device) {
+  const Plan& p = c->plan;
+  const int64_t o2 = c->d.o * c->d.o, v2 = c->d.v * c->d.v;
+  load_device_or_host(c, c->at(p.dt64), dt, (size_t)(o2 * v2) * 8, on_device);
+  check_finite_input(c, c->at<double>(p.dt64), o2 * v2, "dt");
+  transpose_batched(c->at<double>(p.dt64), c->at(p.dt64T), DType::F64, 1, o2, v2, c->stream);
+  if (c->prec == CPPPL_BF16) {
+    convert(c->at<double>(p.dt64), c->at(p.dt16), DType::BF16, o2 * v2, c->stream);
+    transpose_batched(c->at<double>(p.dt64), c->at(p.dt16T), DType::BF16, 1, o2, v2, c->stream);
+  }
+}
+// L = ||CP||^2 - 2 <R, CP> at the current factors (FP64 MTTKRP of alpha).
+double ws_judge_loss(cpppl_ctx* c) {
+  const Plan& p = c->plan;
+  mttkrp_into_MT(c, path_for(c, DType::F64), 2);
+  const double* G[4];
+  for (int m = 0; m < 4; ++m) G[m] = c->at<double>(p.gram[m]);
+  fit_scalars(c->at<double>(p.MT), c->at<double>(p.FT[2]), c->d.v, c->at<double>(p.lam), G,
+              c->d.rank, c->at<double>(p.scal) + S_NORM_R2, c->at<double>(p.rowbuf),
+              c->at<double>(p.scal) + S_JUDGE, c->stream);
+  CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(p.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return c->host_scal[S_JUDGE + 1] - 2.0 * c->host_scal[S_JUDGE];
+}
 void ws_derive_t(cpppl_ctx* c) {
   derive_t(c);
   c->norm_valid = false;

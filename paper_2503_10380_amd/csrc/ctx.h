@@ -27,8 +27,9 @@ struct Plan {
   size_t rowbuf, sums, scal, status;
   // planted CP tensor
   size_t FpT[4], lamp, Cp;
-  // warm start
-  size_t wsF[4], wsLam, wsFeat, wsD[4];
+  // warm start: previous factors, first-order change, features / targets, dt layouts
+  size_t wsF[4], wsLam, wsFeat, wsOut, wsD[4];
+  size_t dt64, dt64T, dt16, dt16T;
 };
 
 enum Scal {  // slots of the device scalar block
@@ -39,6 +40,8 @@ enum Scal {  // slots of the device scalar block
   S_ENERGY = 20,
   S_CP2_PREV = 21,
   S_JUDGE = 24,  // 24..28 judge fit scalars
+  S_WS_SCALE = 30,  // feature / target scale of the warm-start network
+  S_WS_SUMSQ = 32,  // 32..33 scratch for the scale
   S_COUNT = 64
 };
 

@@ -1,24 +1,248 @@
-// Learned warm start (placeholder until the network kernels land).
+// Warm starts across amplitude iterations.
+//
+// The paper's "optimal guess" restarts ALS from the previous converged
+// factors (Section "An improved initial guess strategy").  This file adds two
+// candidates computed from the change of the amplitudes dt:
+//  * first order: the PPL tensor is linear in t, so one matrix-free MTTKRP of
+//    dR (the chain evaluated on dt) at the previous factors, solved with the
+//    previous W, gives the first-order change of each factor column
+//    D_m = M_m(dR) W_m^{-1} / lambda;
+//  * learned: a per-column network maps [previous columns, D columns] of the
+//    four factors to a correction of the previous columns.
+// Features and targets are scaled by s = 1 / rms(D) so the network sees O(1)
+// numbers whatever the size of the step.  A candidate replaces the plain warm
+// start only if it has the lower ||CP||^2 - 2 <R, CP> for the new t.
+#include <cmath>
+#include <limits>
+#include <stdexcept>
+
+#include "mlp.h"
+#include "ops.h"
 #include "ws.h"
 
+using namespace cpppl;
+
+namespace {
+
+constexpr int TPB = 256;
+unsigned nb(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + TPB - 1) / TPB, 1 << 16)); }
+
+// D[r][n] /= lam[r] (zero rows stay zero)
+__global__ void div_rows_kernel(double* D, const double* lam, int64_t R, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double l = lam[e / n];
+    D[e] = l > 0.0 ? D[e] / l : 0.0;
+  }
+}
+
+// acc[0] += sum x^2 (single block, fixed order)
+__global__ __launch_bounds__(TPB) void sumsq_kernel(const double* x, int64_t n, double* acc) {
+  __shared__ double sh[TPB];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += TPB) s += x[i] * x[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = TPB / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[0] += sh[0];
+}
+
+// scale[0] = 1 / sqrt(acc / count), or 1 if that is not a finite positive number
+__global__ void finish_scale_kernel(const double* acc, double count, double* scale) {
+  const double ms = acc[0] / count;
+  const double s = 1.0 / sqrt(ms);
+  scale[0] = (ms > 0.0 && isfinite(s)) ? s : 1.0;
+}
+
+// y[r][off + i] = (float)(x[r][i] * (scale ? *scale : 1))
+__global__ void pack_kernel(const double* x, int64_t R, int64_t n, const double* scale, float* y,
+                            int64_t ldy, int64_t off) {
+  const double s = scale ? scale[0] : 1.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R * n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[(e / n) * ldy + off + e % n] = (float)(x[e] * s);
+}
+
+// F[r][i] = F0[r][i] + (D ? D[r][i] : 0) + (Y ? Y[r][off + i] / scale : 0)
+__global__ void candidate_kernel(const double* F0, const double* D, const float* Y, int64_t ldy,
+                                 int64_t off, const double* scale, int64_t R, int64_t n,
+                                 double* F) {
+  const double inv = scale ? 1.0 / scale[0] : 1.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = F0[e];
+    if (D) v += D[e];
+    if (Y) v += (double)Y[(e / n) * ldy + off + e % n] * inv;
+    F[e] = v;
+  }
+}
+
+// y[r][off + i] *= scale, as float
+__global__ void scale_cols_kernel(float* y, int64_t R, int64_t ldy, int64_t off, int64_t n,
+                                  const double* scale) {
+  const float s = (float)scale[0];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R * n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[(e / n) * ldy + off + e % n] *= s;
+}
+
+void set_candidate(cpppl_ctx* c, const double* const D[4], const float* Y, int64_t ldy,
+                   const double* scale) {
+  const Plan& p = c->plan;
+  const int64_t R = c->d.rank;
+  int64_t off = 0;
+  for (int m = 0; m < 4; ++m) {
+    const int64_t n = ws_nmode(c->d, m);
+    hipLaunchKernelGGL(candidate_kernel, dim3(nb(R * n)), dim3(TPB), 0, c->stream,
+                       c->at<double>(p.wsF[m]), D ? D[m] : nullptr, Y, ldy, off, scale, R, n,
+                       c->at<double>(p.FT[m]));
+    CPPPL_LAUNCH_CHECK("candidate");
+    off += n;
+  }
+  ws_copy(c, p.lam, p.wsLam, (size_t)R * 8);
+  ws_init_after_factors(c);
+}
+
+}  // namespace
+
+#define WS_TRY(c)                                      \
+  if (!(c)) return CPPPL_E_ARG;                        \
+  if ((c)->hip_failed) return CPPPL_E_HIP;             \
+  try {                                                \
+    CPPPL_HIP(hipSetDevice((c)->device));
+#define WS_CATCH(c)                                                      \
+  }                                                                      \
+  catch (const StatusError& e) {                                         \
+    (c)->err = e.msg;                                                    \
+    return e.st;                                                         \
+  }                                                                      \
+  catch (const HipError& e) {                                            \
+    (c)->hip_failed = true;                                              \
+    (c)->err = std::string(e.where) + ": " + hipGetErrorString(e.err);   \
+    return CPPPL_E_HIP;                                                  \
+  }                                                                      \
+  catch (const std::invalid_argument& e) {                               \
+    (c)->err = e.what();                                                 \
+    return CPPPL_E_ARG;                                                  \
+  }                                                                      \
+  catch (const std::exception& e) {                                      \
+    (c)->err = e.what();                                                 \
+    return CPPPL_E_STATE;                                                \
+  }                                                                      \
+  (c)->err.clear();                                                      \
+  return CPPPL_OK;
+
 extern "C" {
+
 CPPPL_API int64_t cpppl_ws_in_dim(const cpppl_dims* d) { return d ? 2 * (2 * d->o + 2 * d->v) : 0; }
 CPPPL_API int64_t cpppl_ws_out_dim(const cpppl_dims* d) { return d ? (2 * d->o + 2 * d->v) : 0; }
-CPPPL_API cpppl_status cpppl_mlp_create(int, int, int, int, int64_t, uint64_t, int, cpppl_mlp** out) {
-  if (out) *out = nullptr;
-  return CPPPL_E_UNSUPPORTED;
+
+CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* c, const double* dt, int on_device,
+                                        int strategy, cpppl_mlp* mlp, int* chosen) {
+  WS_TRY(c)
+  if (!dt) throw std::invalid_argument("dt is NULL");
+  if (strategy < CPPPL_WS_PLAIN || strategy > CPPPL_WS_FIRST_ORDER)
+    throw std::invalid_argument("unknown warm-start strategy");
+  if (!c->ws) throw StatusError(CPPPL_E_STATE, "no workspace bound");
+  if (c->planted || !c->have_t || !c->have_b || !c->have_factors)
+    throw StatusError(CPPPL_E_STATE, "warm start needs t, B and factors");
+  const int64_t in_dim = cpppl_ws_in_dim(&c->d), out_dim = cpppl_ws_out_dim(&c->d);
+  if (strategy == CPPPL_WS_LEARNED) {
+    if (!mlp) throw std::invalid_argument("the learned warm start needs a network");
+    if (mlp->sizes.front() != in_dim || mlp->sizes.back() != out_dim)
+      throw std::invalid_argument("network shape does not match these dims");
+  }
+  const Plan& p = c->plan;
+  const int64_t R = c->d.rank;
+  double* sc = c->at<double>(p.scal);
+
+  // previous (converged) factors
+  for (int m = 0; m < 4; ++m) ws_copy(c, p.wsF[m], p.FT[m], (size_t)(ws_nmode(c->d, m) * R) * 8);
+  ws_copy(c, p.wsLam, p.lam, (size_t)R * 8);
+
+  // first-order change from the MTTKRP of dR at the previous factors
+  ws_load_dt(c, dt, on_device);
+  zero_doubles(sc + S_WS_SUMSQ, 1, c->stream);
+  for (int m = 0; m < 4; ++m) {
+    const int64_t n = ws_nmode(c->d, m);
+    ws_mttkrp_dt(c, m);
+    ws_solve_no_update(c, m, p.wsD[m]);
+    hipLaunchKernelGGL(div_rows_kernel, dim3(nb(R * n)), dim3(TPB), 0, c->stream,
+                       c->at<double>(p.wsD[m]), c->at<double>(p.wsLam), R, n);
+    CPPPL_LAUNCH_CHECK("div_rows");
+    hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(TPB), 0, c->stream, c->at<double>(p.wsD[m]),
+                       R * n, sc + S_WS_SUMSQ);
+    CPPPL_LAUNCH_CHECK("sumsq");
+  }
+  hipLaunchKernelGGL(finish_scale_kernel, dim3(1), dim3(1), 0, c->stream, sc + S_WS_SUMSQ,
+                     (double)(R * out_dim), sc + S_WS_SCALE);
+  CPPPL_LAUNCH_CHECK("finish_scale");
+
+  // features [F_gamma, F_rho, F_alpha, F_beta, s D_gamma, s D_rho, s D_alpha, s D_beta]
+  float* feat = c->at<float>(p.wsFeat);
+  int64_t off = 0;
+  for (int m = 0; m < 4; ++m) {
+    const int64_t n = ws_nmode(c->d, m);
+    hipLaunchKernelGGL(pack_kernel, dim3(nb(R * n)), dim3(TPB), 0, c->stream,
+                       c->at<double>(p.wsF[m]), R, n, (const double*)nullptr, feat, in_dim, off);
+    hipLaunchKernelGGL(pack_kernel, dim3(nb(R * n)), dim3(TPB), 0, c->stream,
+                       c->at<double>(p.wsD[m]), R, n, (const double*)(sc + S_WS_SCALE), feat, in_dim,
+                       out_dim + off);
+    CPPPL_LAUNCH_CHECK("pack");
+    off += n;
+  }
+  if (strategy == CPPPL_WS_LEARNED) mlp_forward_dev(mlp, feat, R, c->at<float>(p.wsOut), c->stream);
+
+  // the new amplitudes: t <- t + dt
+  axpy1(c->at<double>(p.dt64), c->at<double>(p.t64), c->d.o * c->d.o * c->d.v * c->d.v, c->stream);
+  ws_derive_t(c);
+
+  // judge against the plain warm start
+  int pick = CPPPL_WS_PLAIN;
+  if (strategy != CPPPL_WS_PLAIN) {
+    const double l_plain = ws_judge_loss(c);  // factors are still the previous ones
+    const double* D[4];
+    for (int m = 0; m < 4; ++m) D[m] = c->at<double>(p.wsD[m]);
+    if (strategy == CPPPL_WS_FIRST_ORDER)
+      set_candidate(c, D, nullptr, 0, nullptr);
+    else
+      set_candidate(c, nullptr, c->at<float>(p.wsOut), out_dim, sc + S_WS_SCALE);
+    const double l_cand = ws_judge_loss(c);
+    if (std::isfinite(l_cand) && l_cand < l_plain) pick = strategy;
+    else set_candidate(c, nullptr, nullptr, 0, nullptr);
+  }
+  c->ws_valid = true;
+  ws_sync(c);
+  if (chosen) *chosen = pick;
+  WS_CATCH(c)
 }
-CPPPL_API cpppl_status cpppl_mlp_destroy(cpppl_mlp*) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_mlp_num_params(const cpppl_mlp*, int64_t*) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_mlp_get_params(cpppl_mlp*, float*, int) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_mlp_set_params(cpppl_mlp*, const float*, int) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_mlp_forward(cpppl_mlp*, const float*, int64_t, float*, int) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_mlp_grad(cpppl_mlp*, const float*, const float*, int64_t, float*, float*, int) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_mlp_add_rows(cpppl_mlp*, const float*, const float*, int64_t, int) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_mlp_clear_rows(cpppl_mlp*) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_mlp_train(cpppl_mlp*, int, float, int64_t, uint64_t, float*) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_mlp_save(cpppl_mlp*, const char*) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_mlp_load(cpppl_mlp*, const char*) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx*, const double*, int, int, cpppl_mlp*, int*) { return CPPPL_E_UNSUPPORTED; }
-CPPPL_API cpppl_status cpppl_ws_training_rows(cpppl_ctx*, cpppl_mlp*) { return CPPPL_E_UNSUPPORTED; }
+
+CPPPL_API cpppl_status cpppl_ws_training_rows(cpppl_ctx* c, cpppl_mlp* mlp) {
+  WS_TRY(c)
+  if (!mlp) throw std::invalid_argument("mlp is NULL");
+  if (!c->ws_valid) throw StatusError(CPPPL_E_STATE, "no warm start to learn from");
+  const int64_t in_dim = cpppl_ws_in_dim(&c->d), out_dim = cpppl_ws_out_dim(&c->d);
+  if (mlp->sizes.front() != in_dim || mlp->sizes.back() != out_dim)
+    throw std::invalid_argument("network shape does not match these dims");
+  const Plan& p = c->plan;
+  const int64_t R = c->d.rank;
+  float* y = c->at<float>(p.wsOut);
+  int64_t off = 0;
+  for (int m = 0; m < 4; ++m) {  // target = s (aligned converged column - previous column)
+    const int64_t n = ws_nmode(c->d, m);
+    aligned_delta_f32(c->at<double>(p.FT[m]), c->at<double>(p.wsF[m]), R, n, y + off, out_dim,
+                      c->stream);
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(nb(R * n)), dim3(TPB), 0, c->stream, y, R, out_dim,
+                       off, n, (const double*)(c->at<double>(p.scal) + S_WS_SCALE));
+    CPPPL_LAUNCH_CHECK("scale_cols");
+    off += n;
+  }
+  mlp_append_dev(mlp, c->at<float>(p.wsFeat), in_dim, y, out_dim, R, c->stream);
+  ws_sync(c);
+  WS_CATCH(c)
 }
+
+}  // extern "C"

@@ -25,5 +25,10 @@ void ws_ensure_norm(cpppl_ctx* c);
 void ws_copy(cpppl_ctx* c, size_t dst, size_t src, size_t bytes);
 void ws_sync(cpppl_ctx* c);
 int64_t ws_nmode(const cpppl_dims& d, int m);
+// MTTKRP of `mode` with dt (loaded by ws_load_dt) in place of t, into MT.
+void ws_mttkrp_dt(cpppl_ctx* c, int mode);
+void ws_load_dt(cpppl_ctx* c, const double* dt, int on_device);
+// ||CP||^2 - 2 <R, CP> at the current factors (synchronises).
+double ws_judge_loss(cpppl_ctx* c);
 
 }  // namespace cpppl

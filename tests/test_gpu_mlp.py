@@ -1,0 +1,128 @@
+"""The warm-start network's hand-written GPU kernels against the FP64 reference
+(oracle.mlp): forward values, loss and every parameter gradient (FP32 vs
+FP64, relative 1e-4), one Adam step, training progress, save/load."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [80, 256, 256, 40]  # C1 widths: 2(2o+2v) -> 256 -> 256 -> 2o+2v
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+def _rand_params(sizes, seed):
+    rng = np.random.default_rng(seed)
+    ps = []
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        ps.append(rng.uniform(-1, 1, (fo, fi)) / np.sqrt(fi))
+        ps.append(rng.uniform(-0.2, 0.2, fo))
+    return [p.astype(np.float32).astype(np.float64) for p in ps]
+
+
+def _pack(ps):
+    return np.concatenate([p.reshape(-1) for p in ps]).astype(np.float32)
+
+
+def _net(lib, seed=0, capacity=0):
+    return lib.MLP(SIZES[0], SIZES[-1], hidden=SIZES[1], n_hidden=len(SIZES) - 2,
+                   capacity=capacity, seed=seed)
+
+
+def test_untrained_network_predicts_zero(lib):
+    m = _net(lib, seed=3)
+    x = np.random.default_rng(0).standard_normal((17, SIZES[0])).astype(np.float32)
+    np.testing.assert_array_equal(m.forward(x), 0.0)
+    assert m.nparams == sum(fo * fi + fo for fi, fo in zip(SIZES[:-1], SIZES[1:]))
+
+
+def test_forward_matches_reference(lib):
+    _say("mlp forward")
+    m = _net(lib)
+    ps = _rand_params(SIZES, 1)
+    m.set_params(_pack(ps))
+    x = np.random.default_rng(2).standard_normal((70, SIZES[0])).astype(np.float32)
+    want = omlp.forward(ps, x.astype(np.float64))[0]
+    got = m.forward(x)
+    assert np.abs(got - want).max() <= 1e-5 * np.abs(want).max()
+
+
+def test_gradients_match_reference(lib):
+    _say("mlp grad")
+    m = _net(lib)
+    ps = _rand_params(SIZES, 4)
+    m.set_params(_pack(ps))
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((130, SIZES[0])).astype(np.float32)
+    t = rng.standard_normal((130, SIZES[-1])).astype(np.float32)
+    loss, g = m.grad(x, t)
+    want_loss, want_g = omlp.loss_and_grads(ps, x.astype(np.float64), t.astype(np.float64))
+    assert loss == pytest.approx(want_loss, rel=1e-5)
+    off = 0
+    for k, wg in enumerate(want_g):
+        got = g[off:off + wg.size].reshape(wg.shape)
+        off += wg.size
+        err = np.linalg.norm(got - wg) / np.linalg.norm(wg)
+        assert err <= 1e-4, (k, err)
+
+
+def test_one_adam_step_matches_reference(lib):
+    _say("mlp adam")
+    m = _net(lib, capacity=64)
+    ps = _rand_params(SIZES, 6)
+    m.set_params(_pack(ps))
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((64, SIZES[0])).astype(np.float32)
+    t = rng.standard_normal((64, SIZES[-1])).astype(np.float32)
+    m.add_rows(x, t)
+    m.train(1, lr=1e-3)
+    _, g = omlp.loss_and_grads(ps, x.astype(np.float64), t.astype(np.float64))
+    want, _, _ = omlp.adam_step(list(ps), g, [np.zeros_like(p) for p in ps],
+                                [np.zeros_like(p) for p in ps], 1, lr=1e-3)
+    got = m.get_params().astype(np.float64)
+    ref = np.concatenate([p.reshape(-1) for p in want])
+    gref = np.concatenate([x.reshape(-1) for x in g])
+    # the first Adam step moves each weight by lr g / (|g| + eps); compare the
+    # moves where the FP32 and FP64 gradients cannot disagree in sign
+    base = _pack(ps).astype(np.float64)
+    move_got, move_ref = got - base, ref - base
+    sure = np.abs(gref) > 1e-5
+    assert sure.mean() > 0.5
+    assert np.abs(move_got - move_ref)[sure].max() <= 2e-6
+    assert np.abs(move_got).max() <= 1e-3 * (1 + 1e-5)
+
+
+def test_training_reduces_loss_and_minibatches(lib):
+    _say("mlp train")
+    m = _net(lib, capacity=512, seed=11)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((512, SIZES[0])).astype(np.float32)
+    t = (0.5 * np.tanh(x[:, :SIZES[-1]]) + 0.1 * x[:, SIZES[-1]:2 * SIZES[-1]]).astype(np.float32)
+    m.add_rows(x, t)
+    assert m.num_rows == 512
+    hist = m.train(60, lr=1e-3, batch=128, seed=3)
+    assert hist[-1] < 0.5 * hist[0]
+    xs, ys = m.get_rows()
+    np.testing.assert_array_equal(xs, x)
+    np.testing.assert_array_equal(ys, t)
+
+
+def test_save_load_roundtrip(lib, tmp_path):
+    m = _net(lib)
+    ps = _rand_params(SIZES, 9)
+    m.set_params(_pack(ps))
+    path = tmp_path / "net.bin"
+    m.save(path)
+    m2 = _net(lib, seed=99)
+    m2.load(path)
+    np.testing.assert_array_equal(m2.get_params(), m.get_params())
+    bad = lib.MLP(SIZES[0], SIZES[-1], hidden=64, n_hidden=1)
+    with pytest.raises(lib.CppplError):
+        bad.load(path)

@@ -1,0 +1,176 @@
+"""Warm starts across a CCSD-like amplitude sequence, through the C ABI.
+
+Pinned against the oracle: the amplitude update t <- t + dt, the features
+(previous factor columns and the first-order change M(dR) W^{-1} / lambda of
+each factor, with M(dR) the textbook MTTKRP of the explicitly formed PPL
+tensor of dt), the training targets, and the judge (a non-plain candidate is
+kept only when ||CP||^2 - 2 <R, CP> is lower).  The size of the learned
+network's gain is reported; it is not a pinned quantity.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+CFG = synth.custom_config(6, 24, 72, 40, name="ws_small")
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+def _ctx(lib, cfg, t, b, precision="fp64"):
+    ctx = lib.Context(cfg.o, cfg.v, cfg.nx, cfg.rank, precision)
+    ctx.load_t2(t)
+    ctx.load_df(b)
+    return ctx
+
+
+def _gram_w(fs, mode):
+    return oracle.gram_hadamard(fs, mode)
+
+
+def test_plain_warm_start_advances_t_and_keeps_factors(lib):
+    cfg = CFG
+    inp = synth.make_inputs(cfg)
+    fs = synth.init_factors(cfg)
+    dt = synth.perturbation(cfg, 0, inp.t)
+    ctx = _ctx(lib, cfg, inp.t, inp.b_vv)
+    ctx.set_factors(*fs)
+    assert ctx.warm_start(dt, lib.WS_PLAIN) == lib.WS_PLAIN
+    got = ctx.get_factors()
+    for a, b in zip(got[:4], fs):
+        np.testing.assert_array_equal(a, b)
+    r_new = oracle.form_r(inp.t + dt, inp.b_vv)
+    for mode in range(4):
+        want = oracle.mttkrp(r_new, fs, mode)
+        assert np.linalg.norm(ctx.mttkrp(mode) - want) <= 1e-10 * np.linalg.norm(want)
+    n2, e = ctx.norm_r2()
+    assert n2 == pytest.approx(float(np.sum(r_new * r_new)), rel=1e-12)
+
+
+def test_features_and_targets_match_oracle(lib):
+    cfg = CFG
+    _say("warm-start features")
+    inp = synth.make_inputs(cfg)
+    r0 = oracle.form_r(inp.t, inp.b_vv)
+    f0, lam0, _ = oracle.cp_als(r0, synth.init_factors(cfg), 8)
+    dt = synth.perturbation(cfg, 1, inp.t)
+    ctx = _ctx(lib, cfg, inp.t, inp.b_vv)
+    ctx.set_factors(*f0, lam0)
+    net = lib.MLP(ctx.ws_in_dim, ctx.ws_out_dim, capacity=cfg.rank)
+    ctx.warm_start(dt, lib.WS_PLAIN)
+    rep = ctx.als(5)
+    ctx.training_rows(net)
+    x, y = net.get_rows()
+    assert x.shape == (cfg.rank, ctx.ws_in_dim)
+    # previous columns, mode order (i, j, a, b)
+    prev = np.concatenate([f.T for f in f0], axis=1)
+    np.testing.assert_allclose(x[:, :ctx.ws_out_dim], prev, rtol=1e-6, atol=1e-7)
+    # first-order change of every factor from the MTTKRP of dR
+    rd = oracle.form_r(dt, inp.b_vv)
+    d = []
+    for mode in range(4):
+        m = oracle.mttkrp(rd, f0, mode)
+        d.append((m @ np.linalg.inv(_gram_w(f0, mode))) / lam0)
+    d = np.concatenate([q.T for q in d], axis=1)
+    s = 1.0 / np.sqrt(np.mean(d * d))
+    got = x[:, ctx.ws_out_dim:]
+    assert np.abs(got - s * d).max() <= 1e-5 * np.abs(s * d).max()
+    # targets: s (sign-aligned converged column - previous column)
+    fi, fj, fa, fb, _ = ctx.get_factors()
+    new = [fi, fj, fa, fb]
+    tgt = []
+    for f1, f0m in zip(new, f0):
+        sg = np.sign(np.sum(f1 * f0m, axis=0))
+        sg[sg == 0] = 1
+        tgt.append((f1 * sg - f0m).T)
+    tgt = s * np.concatenate(tgt, axis=1)
+    assert np.abs(y - tgt).max() <= 1e-5 * max(1.0, np.abs(tgt).max())
+    assert rep["sweeps"] == 5
+
+
+def test_first_order_candidate_is_judged(lib):
+    cfg = CFG
+    _say("first-order judge")
+    inp = synth.make_inputs(cfg)
+    r0 = oracle.form_r(inp.t, inp.b_vv)
+    f0, lam0, _ = oracle.cp_als(r0, synth.init_factors(cfg), 30)
+    dt = synth.perturbation(cfg, 2, inp.t)
+    r1 = oracle.form_r(inp.t + dt, inp.b_vv)
+    ctx = _ctx(lib, cfg, inp.t, inp.b_vv)
+    ctx.set_factors(*f0, lam0)
+    chosen = ctx.warm_start(dt, lib.WS_FIRST_ORDER)
+    fi, fj, fa, fb, lam = ctx.get_factors()
+    cand = oracle.cp_full((fi, fj, fa, fb), lam)
+    plain = oracle.cp_full(f0, lam0)
+    l_cand = np.sum(cand * cand) - 2 * np.sum(r1 * cand)
+    l_plain = np.sum(plain * plain) - 2 * np.sum(r1 * plain)
+    assert l_cand <= l_plain + 1e-9 * abs(l_plain)
+    if chosen == lib.WS_PLAIN:
+        for a, b in zip((fi, fj, fa, fb), f0):
+            np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)
+    _say(f"  chosen={chosen} L_plain={l_plain:.6e} L_cand={l_cand:.6e}")
+
+
+def _sweeps_to(fits, target, rel=1e-4):
+    for k, f in enumerate(fits):
+        if abs(f - target) <= rel * abs(target):
+            return k + 1
+    return len(fits) + 1
+
+
+def test_learned_warm_start_sequence(lib):
+    """Train on the warm starts of steps 1-6 of an amplitude sequence, evaluate
+    plain / first-order / learned on steps 7-10 from the same converged start."""
+    cfg = CFG
+    _say("learned warm-start sequence")
+    inp = synth.make_inputs(cfg)
+    ts = [inp.t] + list(synth.amplitude_sequence(cfg, inp.t, 10, period=6))
+    ctx = _ctx(lib, cfg, ts[0], inp.b_vv)
+    ctx.set_factors(*synth.init_factors(cfg))
+    ctx.als(400, stop_rule=1, tol=1e-9)
+    net = lib.MLP(ctx.ws_in_dim, ctx.ws_out_dim, capacity=10 * cfg.rank, seed=5)
+    for k in range(1, 7):
+        ctx.warm_start(ts[k] - ts[k - 1], lib.WS_PLAIN)
+        ctx.als(400, stop_rule=1, tol=1e-9)
+        ctx.training_rows(net)
+    hist = net.train(300, lr=1e-3, batch=64, seed=1)
+    assert hist[-1] < hist[0]
+    report = []
+    for k in range(7, 11):
+        state = ctx.get_factors()
+        res = {}
+        for name, strat in (("plain", lib.WS_PLAIN), ("first_order", lib.WS_FIRST_ORDER),
+                            ("learned", lib.WS_LEARNED)):
+            ctx.load_t2(ts[k - 1])
+            ctx.set_factors(*state)
+            chosen = ctx.warm_start(ts[k] - ts[k - 1], strat, net if strat == lib.WS_LEARNED else None)
+            rep = ctx.als(400, stop_rule=1, tol=1e-9)
+            res[name] = (chosen, rep["fit_hist"])
+        target = res["plain"][1][-1]
+        # (chosen, sweeps to within 1e-4 of the plain converged fit, sweeps to
+        #  |dfit| < 1e-9, gap of the first-sweep fit, final fit)
+        row = {n: (c, _sweeps_to(h, target), len(h), abs(h[0] - target) / abs(target), h[-1])
+               for n, (c, h) in res.items()}
+        report.append(row)
+        _say(f"  step {k}: " + ", ".join(
+            f"{n}: chosen={c} to1e-4={s} converged={nc} gap1={g:.2e}"
+            for n, (c, s, nc, g, f) in row.items()))
+        # every warm start converges to the same fit within the stopping noise
+        for n, (c, s, nc, g, f) in row.items():
+            assert abs(f - target) <= 1e-4 * abs(target)
+        ctx.load_t2(ts[k - 1])
+        ctx.set_factors(*state)
+        ctx.warm_start(ts[k] - ts[k - 1], lib.WS_PLAIN)
+        ctx.als(400, stop_rule=1, tol=1e-9)
+    for idx, what in ((1, "sweeps to within 1e-4"), (2, "sweeps to |dfit|<1e-9"),
+                      (3, "first-sweep fit gap")):
+        mean = {n: float(np.mean([r[n][idx] for r in report])) for n in report[0]}
+        _say(f"  mean {what}: {mean}")
