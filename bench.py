@@ -3,7 +3,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C3]
 
 A step is one ALS sweep of the BF16-operand path (FP32 accumulation; FP64
-Grams, Cholesky solves, normalisation, fit and eta): the four matrix-free
+Grams, block-sweep inverses, solves, normalisation, fit and eta): the four matrix-free
 MTTKRP chains and the four factor updates, on synthetic MP2-shaped inputs
 already resident in HBM.  The one-time ||R||^2 pass, the FP64 refinement sweep,
 the energy contraction and the plain-FP64 comparison are timed separately and
@@ -126,6 +126,9 @@ def main():
     ap.add_argument("--compare-sweeps", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run three plain device copies of MIB MiB each, so that "
+                         "HBM byte counters can be scaled against a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -134,6 +137,17 @@ def main():
 
     import torch
     import paper_2503_10380_amd as cp
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy calibration: 3 copies of {args.copy_calibration} MiB", file=sys.stderr)
+        del src, dst
 
     cfg = synth.CONFIGS[args.config]
     inp = synth.make_inputs(cfg)

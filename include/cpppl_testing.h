@@ -26,8 +26,9 @@ CPPPL_API cpppl_status cpppl_test_gemm(int in_dtype, int64_t M, int64_t N, int64
                                        void* C, int64_t scm, int64_t scb, int c_dtype, double alpha,
                                        double beta, int splits, void* partial, void* stream);
 
-/* Y (R x n) = W^{-1} X for SPD W (R x R, overwritten; `work` holds R*R
- * doubles) by the block sweep-operator inverse; status: 0 ok, 1 bad pivot. */
+/* Y (R x n) = W^{-1} X for SPD W (R x R, overwritten; `work` holds
+ * R*R + 8192 doubles) by the block sweep-operator inverse; status: 0 ok,
+ * 1 bad pivot. */
 CPPPL_API cpppl_status cpppl_test_spd_solve(double* W, int64_t R, const double* X, double* Y,
                                             int64_t n, double* work, int* status, void* stream);
 

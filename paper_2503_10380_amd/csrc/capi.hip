@@ -79,6 +79,7 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   p.Cp = add((size_t)R * R * 8);
   p.invA = add((size_t)R * R * 8);
   p.invB = add((size_t)R * R * 8);
+  p.invD = add((size_t)INV_DBUF * 8);
   const int64_t nmax = std::max(o, v);
   p.MT = add((size_t)nmax * R * 8);
   p.stage = add((size_t)std::max<int64_t>(nmax * R, R * R) * 8);
@@ -359,7 +360,8 @@ int prepare_inverse(cpppl_ctx* c, int m, hipStream_t st, bool careful) {
     hadamard(G[0], G[1], G[2], c->at<double>(p.invA), R * R, st);
     if (attempt > 0) add_ridge(c->at<double>(p.invA), R, 1e-14 * std::pow(100.0, attempt - 1), st);
     if (careful) zero_ints(c->at<int>(p.status), 1, st);
-    c->inv = spd_inverse_neg(c->at<double>(p.invA), c->at<double>(p.invB), R, c->at<int>(p.status), st);
+    c->inv = spd_inverse_neg(c->at<double>(p.invA), c->at<double>(p.invB), c->at<double>(p.invD), R,
+                             c->at<int>(p.status), st);
     if (!careful) break;
     CPPPL_HIP(hipStreamSynchronize(st));
     if (read_status(c) == 0) break;
@@ -379,6 +381,11 @@ void apply_inverse(cpppl_ctx* c, int m) {
   g.A = c->inv; g.sam = R; g.sak = 1;
   g.B = c->at(p.MT); g.sbk = n; g.sbn = 1;
   g.C = c->at(p.FT[m]); g.scm = n; g.ctype = DType::F64; g.alpha = -1.0;
+  // few output tiles (R x n): split K so that the launch fills the chip
+  int s = choose_splits(gemm_tiles_f64(R, n), R, 256, 64, 16);
+  const int64_t cap = (int64_t)(p.partial_elems / (size_t)(R * n));
+  g.splits = (int)std::max<int64_t>(1, std::min<int64_t>(s, cap));
+  g.partial = c->at(p.partial);
   gemm_f64(g, c->stream);
   row_normalize(c->at<double>(p.FT[m]), R, n, c->at<double>(p.lam), c->stream);
   compute_gram(c, m);

@@ -19,7 +19,7 @@ struct Plan {
   size_t t16, t16T, b16T, b16P;
   // factors (transposed, R x n), weights, snapshots, Grams
   size_t FT[4], FTprev[4], F16T[4], lam, lamprev;
-  size_t gram[4], cross[4], invA, invB, MT, stage;
+  size_t gram[4], cross[4], invA, invB, invD, MT, stage;
   // intermediates: one region [tau | Ya | Yb | Z]; G aliases Z
   size_t big, tau, Ya, Yb, Z;
   size_t big_bytes;

@@ -41,7 +41,7 @@ CPPPL_API cpppl_status cpppl_test_spd_solve(double* W, int64_t R, const double* 
                                             int64_t n, double* work, int* status, void* stream) {
   try {
     hipStream_t s = (hipStream_t)stream;
-    double* inv = spd_inverse_neg(W, work, R, status, s);
+    double* inv = spd_inverse_neg(W, work, work + R * R, R, status, s);
     Gemm g;
     g.M = R; g.N = n; g.K = R;
     g.A = inv; g.sam = R; g.sak = 1;

@@ -101,7 +101,7 @@ def test_spd_inverse_solve(env, R, n):
     tw = torch.tensor(w).cuda()
     tx = torch.tensor(x).cuda()
     ty = torch.zeros((R, n), dtype=torch.float64, device="cuda")
-    work = torch.zeros(R * R, dtype=torch.float64, device="cuda")
+    work = torch.zeros(R * R + 8192, dtype=torch.float64, device="cuda")
     status = torch.zeros(4, dtype=torch.int32, device="cuda")
     st = L.cpppl_test_spd_solve(tw.data_ptr(), R, tx.data_ptr(), ty.data_ptr(), n, work.data_ptr(),
                                 status.data_ptr(), torch.cuda.current_stream().cuda_stream)
@@ -120,7 +120,7 @@ def test_spd_inverse_flags_indefinite(env):
     tw = torch.tensor(w).cuda()
     tx = torch.ones((R, 2), dtype=torch.float64, device="cuda")
     ty = torch.zeros((R, 2), dtype=torch.float64, device="cuda")
-    work = torch.zeros(R * R, dtype=torch.float64, device="cuda")
+    work = torch.zeros(R * R + 8192, dtype=torch.float64, device="cuda")
     status = torch.zeros(4, dtype=torch.int32, device="cuda")
     st = L.cpppl_test_spd_solve(tw.data_ptr(), R, tx.data_ptr(), ty.data_ptr(), 2, work.data_ptr(),
                                 status.data_ptr(), torch.cuda.current_stream().cuda_stream)
