@@ -185,8 +185,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const KArgs a) {
 }
 
 // ------------------------------------------------------------------ BF16 ----
-constexpr int BBK = 64;         // K slice
-constexpr int BLDK = BBK + 8;   // padded LDS row (bf16 elements)
+// K slice: 32 for short K (4 work-groups per CU hide more latency), 64 for
+// long K per split (fewer barriers per flop).
+constexpr int BBK_SHORT = 32, BBK_LONG = 64;
+constexpr int64_t BBK_LONG_MIN_K = 2048;
 
 // 8 bf16 at p[0], p[step], ... with the elements at index >= count set to 0.
 __device__ __forceinline__ uint4 gather8(const bf16_t* p, int64_t step, int64_t count) {
@@ -200,13 +202,26 @@ __device__ __forceinline__ uint4 gather8(const bf16_t* p, int64_t step, int64_t 
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// One operand tile (ROWS x BBK) of a BF16 GEMM: global -> registers -> LDS
-// (LDS layout [row][k] with padded rows).  KC: the operand's unit stride is
-// along k; otherwise along the row index and the tile is transposed on its
-// way into LDS.
-template <int ROWS, bool KC>
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+// ds_read_b64_tr_b16: within each group of 16 lanes, lane i receives element
+// i % 4 of the 8 bytes addressed by lane 4 c + i / 4 as its component c.
+__device__ __forceinline__ s4_t lds_read_tr(const bf16_t* p) {
+  typedef __attribute__((address_space(3))) s4_t lds_s4;
+  return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(__attribute__((address_space(3))) void*)p);
+}
+
+// One operand tile (ROWS x BBK) of a BF16 GEMM: global -> registers -> LDS.
+// KC: the operand's unit stride is along k; the tile is kept [row][k] with
+// padded rows and a fragment is one 16-byte read.  Otherwise the unit stride
+// is along the row index; the tile is kept [k][row] (16-byte stores straight
+// from the coalesced loads) and a fragment is two transposing reads.
+template <int ROWS, bool KC, int BBK>
 struct BfTile {
+  static constexpr int BLDK = BBK + 8;  // padded row of the [row][k] layout
   static constexpr int C = ROWS * BBK / 8 / 256;
+  static constexpr int LDT = ROWS + 8;
+  static constexpr int SIZE = KC ? ROWS * BLDK : BBK * LDT;  // bf16 elements per buffer
   __device__ __forceinline__ static void load(uint4 (&r)[C], const bf16_t* X, int64_t s_row,
                                               int64_t s_k, int64_t row0, int64_t nrows, int64_t k0,
                                               int64_t kend, bool vec, int tid) {
@@ -237,13 +252,23 @@ struct BfTile {
         *(uint4*)&S[row * BLDK + kk] = r[e];
       } else {
         const int kk = c / (ROWS / 8), row = (c % (ROWS / 8)) * 8;
-        const uint32_t w[4] = {r[e].x, r[e].y, r[e].z, r[e].w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          S[(row + 2 * q) * BLDK + kk] = (bf16_t)(w[q] & 0xffffu);
-          S[(row + 2 * q + 1) * BLDK + kk] = (bf16_t)(w[q] >> 16);
-        }
+        *(uint4*)&S[kk * LDT + row] = r[e];
       }
+    }
+  }
+  // Matrix-core fragment of rows row0 .. row0 + 15, k = ks .. ks + 31: lane l
+  // gets row row0 + l % 16, k = ks + 8 (l / 16) .. + 7.
+  __device__ __forceinline__ static bf16x8_t frag(const bf16_t* S, int row0, int ks, int lane) {
+    if (KC) {
+      return *(const bf16x8_t*)&S[(row0 + (lane & 15)) * BLDK + ks + 8 * (lane >> 4)];
+    } else {
+      const int s = lane & 15;
+      const bf16_t* p = &S[(ks + 8 * (lane >> 4) + (s >> 2)) * LDT + row0 + 4 * (s & 3)];
+      const s4_t lo = lds_read_tr(p);
+      const s4_t hi = lds_read_tr(p + 4 * LDT);
+      typedef short s8_t __attribute__((ext_vector_type(8)));
+      const s8_t v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      return __builtin_bit_cast(bf16x8_t, v);
     }
   }
 };
@@ -254,17 +279,21 @@ template <> __device__ __forceinline__ float to_out<float>(float v) { return v; 
 template <> __device__ __forceinline__ bf16_t to_out<bf16_t>(float v) { return f32_to_bf16(v); }
 template <> __device__ __forceinline__ double to_out<double>(float v) { return (double)v; }
 
-template <int BM, int BN, bool AK, bool BKC, typename OutT>
-__global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(const KArgs a) {
+template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT>
+__global__ __launch_bounds__(256, BBK == BBK_LONG ? 2 : ((AK && BKC) ? 4 : 3))
+void gemm_bf16_kernel(const KArgs a) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int AS = BM * BLDK, BS = BN * BLDK;  // bf16 elements per buffer
-  // staged epilogue: OutT (or float for split-K partials) tile with padded rows
+  using TA = BfTile<BM, AK, BBK>;
+  using TB = BfTile<BN, BKC, BBK>;
+  constexpr int AS = TA::SIZE, BS = TB::SIZE;  // bf16 elements per buffer
+  // staged epilogue: 2-byte results in one pass, 4-byte results (FP32 output
+  // or split-K partials) in two passes of BM / 2 rows
   constexpr bool STAGE = sizeof(OutT) <= 4;
-  constexpr int ESZ = sizeof(OutT) <= 4 ? (int)sizeof(OutT) : 4;
-  constexpr int LDC = BN + 16 / ESZ;
+  constexpr int LDC2 = BN + 8, LDC4 = BN + 4;
   constexpr int SMEM_AB = 2 * (AS + BS) * 2;
-  constexpr int SMEM_C = STAGE ? BM * LDC * ESZ : 0;
+  constexpr int SMEM_C2 = BM * LDC2 * 2, SMEM_C4 = (BM / 2) * LDC4 * 4;
+  constexpr int SMEM_C = SMEM_C2 > SMEM_C4 ? SMEM_C2 : SMEM_C4;
   constexpr int SMEM = SMEM_AB > SMEM_C ? SMEM_AB : SMEM_C;
   __shared__ __attribute__((aligned(16))) char smem[SMEM];
   bf16_t* As = (bf16_t*)smem;             // [2][AS]
@@ -279,8 +308,6 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(const KArgs a) {
   const bf16_t* A = (const bf16_t*)a.A + tc.b * a.sab;
   const bf16_t* B = (const bf16_t*)a.B + tc.b * a.sbb;
   const bool vec = a.vec_ok != 0;
-  using TA = BfTile<BM, AK>;
-  using TB = BfTile<BN, BKC>;
   const int64_t sa_row = AK ? a.sam : 1, sa_k = AK ? 1 : a.sak;
   const int64_t sb_row = BKC ? a.sbn : 1, sb_k = BKC ? 1 : a.sbk;
 
@@ -299,7 +326,6 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(const KArgs a) {
     TB::store(rb, Bs, tid);
   }
   __syncthreads();
-  const int fr = lane & 15, fk = 8 * (lane >> 4);
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = (int)(kt & 1);
     const bf16_t* Ac = As + cur * AS;
@@ -313,11 +339,9 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(const KArgs a) {
     for (int ks = 0; ks < BBK; ks += 32) {
       bf16x8_t af[TM], bfr[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
-        af[i] = *(const bf16x8_t*)&Ac[(wm * WM + i * 16 + fr) * BLDK + ks + fk];
+      for (int i = 0; i < TM; ++i) af[i] = TA::frag(Ac, wm * WM + i * 16, ks, lane);
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
-        bfr[j] = *(const bf16x8_t*)&Bc[(wn * WN + j * 16 + fr) * BLDK + ks + fk];
+      for (int j = 0; j < TN; ++j) bfr[j] = TB::frag(Bc, wn * WN + j * 16, ks, lane);
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -336,50 +360,69 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(const KArgs a) {
   if constexpr (STAGE) {
     // Stage the tile through LDS (the K-loop buffers are free after the last
     // barrier) and write whole 16-byte row chunks.
-    using ST = typename std::conditional<sizeof(OutT) <= 4, OutT, float>::type;
     const bool part = a.splits > 1;
-    ST* Cs = (ST*)smem;
-    const float alpha = part ? 1.0f : (float)a.alpha;
+    if (!part && sizeof(OutT) == 2) {
+      bf16_t* Cs = (bf16_t*)smem;
+      const float alpha = (float)a.alpha;
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int lm = wm * WM + i * 16 + 4 * (lane >> 4) + r;
-          const int ln = wn * WN + j * 16 + (lane & 15);
-          if (part) ((float*)smem)[lm * (BN + 4) + ln] = acc[i][j][r];
-          else Cs[lm * LDC + ln] = to_out<ST>(alpha * acc[i][j][r]);
-        }
-    __syncthreads();
-    if (part) {
-      constexpr int EPC = 4, CPR = BN / EPC;
-      float* dst = (float*)a.partial + ((int64_t)tc.split * a.batch + tc.b) * a.M * a.N;
-      const float* src = (const float*)smem;
+          for (int r = 0; r < 4; ++r) {
+            const int lm = wm * WM + i * 16 + 4 * (lane >> 4) + r;
+            const int ln = wn * WN + j * 16 + (lane & 15);
+            Cs[lm * LDC2 + ln] = f32_to_bf16(alpha * acc[i][j][r]);
+          }
+      __syncthreads();
+      constexpr int EPC = 8, CPR = BN / EPC;
+      bf16_t* dst = (bf16_t*)a.C + tc.b * a.scb;
       for (int c = tid; c < BM * CPR; c += 256) {
         const int row = c / CPR, col = (c % CPR) * EPC;
         const int64_t gm = m0 + row, gn = n0 + col;
         if (gm >= a.M) continue;
         if (a.cvec_ok && gn + EPC <= a.N) {
-          *(uint4*)(dst + gm * a.N + gn) = *(const uint4*)(src + row * (BN + 4) + col);
+          *(uint4*)(dst + gm * a.scm + gn) = *(const uint4*)(Cs + row * LDC2 + col);
         } else {
           for (int q = 0; q < EPC; ++q)
-            if (gn + q < a.N) dst[gm * a.N + gn + q] = src[row * (BN + 4) + col + q];
+            if (gn + q < a.N) dst[gm * a.scm + gn + q] = Cs[row * LDC2 + col + q];
         }
       }
     } else {
-      constexpr int EPC = 16 / (int)sizeof(ST), CPR = BN / EPC;
-      ST* dst = (ST*)a.C + tc.b * a.scb;
-      for (int c = tid; c < BM * CPR; c += 256) {
-        const int row = c / CPR, col = (c % CPR) * EPC;
-        const int64_t gm = m0 + row, gn = n0 + col;
-        if (gm >= a.M) continue;
-        if (a.cvec_ok && gn + EPC <= a.N) {
-          *(uint4*)(dst + gm * a.scm + gn) = *(const uint4*)(Cs + row * LDC + col);
-        } else {
-          for (int q = 0; q < EPC; ++q)
-            if (gn + q < a.N) dst[gm * a.scm + gn + q] = Cs[row * LDC + col + q];
+      // FP32 results: split-K partials (row stride N, alpha applied later) or C
+      float* Cs = (float*)smem;
+      const float alpha = part ? 1.0f : (float)a.alpha;
+      float* dst = part ? (float*)a.partial + ((int64_t)tc.split * a.batch + tc.b) * a.M * a.N
+                        : (float*)a.C + tc.b * a.scb;
+      const int64_t ldd = part ? a.N : a.scm;
+      constexpr int EPC = 4, CPR = BN / EPC;
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
+        if (wm == pass) {
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int lm = i * 16 + 4 * (lane >> 4) + r;
+                const int ln = wn * WN + j * 16 + (lane & 15);
+                Cs[lm * LDC4 + ln] = alpha * acc[i][j][r];
+              }
         }
+        __syncthreads();
+        for (int c = tid; c < (BM / 2) * CPR; c += 256) {
+          const int row = c / CPR, col = (c % CPR) * EPC;
+          const int64_t gm = m0 + pass * (BM / 2) + row, gn = n0 + col;
+          if (gm >= a.M) continue;
+          if (a.cvec_ok && gn + EPC <= a.N) {
+            *(uint4*)(dst + gm * ldd + gn) = *(const uint4*)(Cs + row * LDC4 + col);
+          } else {
+            for (int q = 0; q < EPC; ++q)
+              if (gn + q < a.N) dst[gm * ldd + gn + q] = Cs[row * LDC4 + col + q];
+          }
+        }
+        __syncthreads();
       }
     }
   } else {
@@ -485,22 +528,33 @@ void gemm_f64(const Gemm& g, hipStream_t s) {
   if (a.splits > 1) launch_reduce<double, double>(a, s);
 }
 
-template <bool AK, bool BKC>
+template <int BK, bool AK, bool BKC>
 static void launch_bf16(const KArgs& a, DType ct, dim3 grid, hipStream_t s) {
   constexpr int BM = 128, BN = 128;
   if (ct == DType::F32 || a.splits > 1)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, AK, BKC, float>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, float>), grid, dim3(256), 0, s, a);
   else if (ct == DType::BF16)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, AK, BKC, bf16_t>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, bf16_t>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, AK, BKC, double>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, double>), grid, dim3(256), 0, s, a);
+}
+
+template <int BK>
+static void launch_bf16_layout(const KArgs& a, bool ak, bool bk, DType ct, dim3 grid,
+                               hipStream_t s) {
+  if (ak && bk) launch_bf16<BK, true, true>(a, ct, grid, s);
+  else if (ak && !bk) launch_bf16<BK, true, false>(a, ct, grid, s);
+  else if (!ak && bk) launch_bf16<BK, false, true>(a, ct, grid, s);
+  else launch_bf16<BK, false, false>(a, ct, grid, s);
 }
 
 void gemm_bf16(const Gemm& g, hipStream_t s) {
   check_operand_strides(g);
   if (g.beta != 0.0 && g.splits <= 1) throw std::invalid_argument("gemm_bf16: beta must be 0");
   constexpr int BM = 128, BN = 128;
-  KArgs a = make_args(g, BM, BN, 64);
+  const int64_t kper = (g.K + std::max(1, g.splits) - 1) / std::max(1, g.splits);
+  const int bk_slice = kper >= BBK_LONG_MIN_K ? BBK_LONG : BBK_SHORT;
+  KArgs a = make_args(g, BM, BN, bk_slice);
   if (a.splits > 1 && !a.partial) throw std::invalid_argument("gemm_bf16: split-K needs a partial buffer");
   const bool ak = g.sak == 1, bk = g.sbk == 1;
   // 16-byte vector loads need 16-byte aligned rows along the contiguous index.
@@ -518,10 +572,8 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
   if (blocks == 0) return;
   if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_bf16: grid too large");
   dim3 grid((unsigned)blocks);
-  if (ak && bk) launch_bf16<true, true>(a, g.ctype, grid, s);
-  else if (ak && !bk) launch_bf16<true, false>(a, g.ctype, grid, s);
-  else if (!ak && bk) launch_bf16<false, true>(a, g.ctype, grid, s);
-  else launch_bf16<false, false>(a, g.ctype, grid, s);
+  if (bk_slice == BBK_LONG) launch_bf16_layout<BBK_LONG>(a, ak, bk, g.ctype, grid, s);
+  else launch_bf16_layout<BBK_SHORT>(a, ak, bk, g.ctype, grid, s);
   CPPPL_LAUNCH_CHECK("gemm_bf16");
   if (a.splits > 1) {
     if (g.ctype == DType::F32) launch_reduce<float, float>(a, s);
