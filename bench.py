@@ -64,22 +64,92 @@ def sweep_flops(cfg):
     return 4.0 * o * o * v * v * r + 14.0 * x * v * v * r
 
 
+def gemm_src_hash():
+    with open(GEMM_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
 def traffic_for(kernel):
-    """HBM bytes per launch from committed counter runs, if they were taken on
-    the current GEMM source; None otherwise."""
+    """HBM bytes per launch of a kernel class from committed counter runs, if
+    they were taken on the current GEMM source; None otherwise."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         rec = json.load(f)
-    with open(GEMM_SRC, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()[:16]
-    if rec.get("gemm_src_sha256_16") != h:
+    if rec.get("gemm_src_sha256_16") != gemm_src_hash():
         return None
-    k = rec.get("kernels", {}).get(kernel)
+    k = rec.get("classes", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, inp, fs, occ=4):
+# BF16 GEMM launches of one ALS sweep in issue order (main stream).
+SWEEP_GEMMS = ["kr_t2", "z", "m", "y", "z", "m", "y", "g", "h"]
+
+
+def digest_counters(fetch_csv, write_csv, steps, calib_mib, out_path):
+    """HBM traffic per MTTKRP kernel class from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
+    `bench.py --steps S --warmup W --no-cpu --no-compare --copy-calibration MIB`.
+    The last 9 S BF16 GEMM dispatches are the timed sweeps, labelled by the
+    fixed issue order; a split-K reduction is charged to the GEMM before it.
+    Each counter is scaled by (known bytes / counted bytes) of the plain device
+    copies of MIB MiB issued first."""
+    import csv
+
+    def per_dispatch(path):
+        rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
+        return [(r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0) for r in rows]
+
+    out = {"gemm_src_sha256_16": gemm_src_hash(), "classes": {}, "calibration": {}}
+    per = {}
+    for name, path in (("fetch", fetch_csv), ("write", write_csv)):
+        d = per_dispatch(path)
+        copies = [b for k, b in d if "copyBuffer" in k or "copy" in k.lower()][:3]
+        known = calib_mib * (1 << 20)
+        big = [b for b in copies if b > 0.25 * known]
+        if not big:
+            raise SystemExit(f"no copy-calibration dispatch found in {path}")
+        factor = known / (sum(big) / len(big))
+        out["calibration"][name] = {"known_bytes": known, "counted_bytes": sum(big) / len(big),
+                                    "factor": factor}
+        idx = [i for i, (k, _) in enumerate(d) if k.startswith("gemm_bf16_kernel")]
+        idx = idx[-9 * steps:]
+        for n, i in enumerate(idx):
+            cls = SWEEP_GEMMS[n % 9]
+            b = d[i][1]
+            if i + 1 < len(d) and d[i + 1][0].startswith("splitk_reduce_kernel"):
+                b += d[i + 1][1]
+            per.setdefault(cls, {}).setdefault(name, []).append(b * factor)
+    for cls, v in per.items():
+        f = sum(v["fetch"]) / len(v["fetch"])
+        w = sum(v["write"]) / len(v["write"])
+        out["classes"][cls] = {"fetch_bytes_per_launch": f, "write_bytes_per_launch": w,
+                               "bytes_per_launch": f + w, "launches": len(v["fetch"])}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def roofline_for(cls, flops, nbytes, launch_ms):
+    """Roofline of one kernel class: bound by whichever of dense-BF16 MFMA time
+    and HBM time is larger for its algorithmic flops and bytes."""
+    t_mfma = flops / (PEAK["bf16"] * 1e12)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    sec = launch_ms * 1e-3
+    if t_hbm >= t_mfma:
+        ach = nbytes / sec / 1e9
+        return {"bound": "hbm", "kernel": cls, "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(cls),
+                "algorithmic_bytes_per_launch": nbytes, "algorithmic_flops_per_launch": flops,
+                "avg_launch_ms": launch_ms, "tflops": flops / sec / 1e12}
+    ach = flops / sec / 1e12
+    return {"bound": "mfma", "kernel": cls, "achieved": ach, "peak": PEAK["bf16"],
+            "unit": "TFLOP/s", "frac": ach / PEAK["bf16"], "traffic": traffic_for(cls),
+            "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
+            "avg_launch_ms": launch_ms, "hbm_gbs": nbytes / sec / 1e9}
+
+
+def cpu_baseline(cfg, inp, fs, occ=8):
     """The FP64 oracle on a bounded sample: R for the i, j < occ pairs, then one
     textbook ALS sweep on that sub-tensor.  MTTKRP work is linear in the number
     of (i, j) pairs, so it is scaled by (o/occ)^2; the R x R solves are not."""
@@ -126,10 +196,17 @@ def main():
     ap.add_argument("--compare-sweeps", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
+                         "script into profiles/traffic_counters.json and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run three plain device copies of MIB MiB each, so that "
                          "HBM byte counters can be scaled against a kernel of known traffic")
     args = ap.parse_args()
+    if args.digest_counters:
+        digest_counters(args.digest_counters[0], args.digest_counters[1], args.steps,
+                        args.copy_calibration, TRAFFIC_FILE)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the sharded design over rank columns is described, not built).", file=sys.stderr)
@@ -190,14 +267,12 @@ def main():
     mttkrp_tflops = sweep_flops(cfg) * args.steps / (mttkrp_ms * 1e-3) / 1e12
     dom = max(CLASSES, key=lambda k: rep["ms_class"][k])
     d_launch_ms = rep["ms_class"][dom] / rep["n_class"][dom]
-    achieved = flops[dom] / (d_launch_ms * 1e-3) / 1e12
-    traffic = traffic_for(dom)
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK["bf16"],
-                "unit": "TFLOP/s", "frac": achieved / PEAK["bf16"], "traffic": traffic,
-                "algorithmic_flops_per_launch": flops[dom],
-                "algorithmic_bytes_per_launch": nbytes[dom],
-                "avg_launch_ms": d_launch_ms,
-                "hbm_gbs_algorithmic": nbytes[dom] / (d_launch_ms * 1e-3) / 1e9}
+    roofline = roofline_for(dom, flops[dom], nbytes[dom], d_launch_ms)
+    for k in CLASSES:
+        if per_class[k]["ms_per_launch"]:
+            r = roofline_for(k, flops[k], nbytes[k], per_class[k]["ms_per_launch"])
+            per_class[k].update({"bound": r["bound"], "frac": r["frac"],
+                                 "gbs": nbytes[k] / (per_class[k]["ms_per_launch"] * 1e-3) / 1e9})
 
     out = {
         "metric": METRIC, "value": args.steps / wall, "unit": "sweeps/s", "n_gpus": 1,
