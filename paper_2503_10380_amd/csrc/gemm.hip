@@ -212,16 +212,26 @@ __device__ __forceinline__ s4_t lds_read_tr(const bf16_t* p) {
 }
 
 // One operand tile (ROWS x BBK) of a BF16 GEMM: global -> registers -> LDS.
-// KC: the operand's unit stride is along k; the tile is kept [row][k] with
-// padded rows and a fragment is one 16-byte read.  Otherwise the unit stride
-// is along the row index; the tile is kept [k][row] (16-byte stores straight
-// from the coalesced loads) and a fragment is two transposing reads.
+// KC: the operand's unit stride is along k; the tile is kept [row][k] and a
+// fragment is one 16-byte read.  With BBK = 32 the rows are unpadded (64 bytes)
+// and the 16-byte chunk index is XOR-ed with bits 2-3 of the row, so both the
+// stores (4 rows x 4 chunks per 16 lanes) and the fragment reads (16 rows, one
+// chunk) hit distinct banks; with BBK = 64 rows are padded to 144 bytes.
+// Otherwise the unit stride is along the row index; the tile is kept [k][row]
+// (16-byte stores straight from the coalesced loads, rows padded to 288 bytes so
+// the 16 rows read by one transposing instruction fall on disjoint bank groups)
+// and a fragment is two transposing reads.
 template <int ROWS, bool KC, int BBK>
 struct BfTile {
-  static constexpr int BLDK = BBK + 8;  // padded row of the [row][k] layout
+  static constexpr bool SWZ = BBK == 32;              // XOR-swizzled [row][k] layout
+  static constexpr int BLDK = SWZ ? BBK : BBK + 8;      // row pitch of the [row][k] layout
   static constexpr int C = ROWS * BBK / 8 / 256;
-  static constexpr int LDT = ROWS + 8;
+  static constexpr int LDT = ROWS + 16;                 // row pitch of the [k][row] layout
   static constexpr int SIZE = KC ? ROWS * BLDK : BBK * LDT;  // bf16 elements per buffer
+  // element offset of (row, kk) in the [row][k] layout, kk a multiple of 8
+  __device__ __forceinline__ static int kc_off(int row, int kk) {
+    return SWZ ? row * BLDK + (((kk >> 3) ^ ((row >> 2) & 3)) << 3) : row * BLDK + kk;
+  }
   __device__ __forceinline__ static void load(uint4 (&r)[C], const bf16_t* X, int64_t s_row,
                                               int64_t s_k, int64_t row0, int64_t nrows, int64_t k0,
                                               int64_t kend, bool vec, int tid) {
@@ -249,7 +259,7 @@ struct BfTile {
       const int c = tid + e * 256;
       if (KC) {
         const int row = c / (BBK / 8), kk = (c % (BBK / 8)) * 8;
-        *(uint4*)&S[row * BLDK + kk] = r[e];
+        *(uint4*)&S[kc_off(row, kk)] = r[e];
       } else {
         const int kk = c / (ROWS / 8), row = (c % (ROWS / 8)) * 8;
         *(uint4*)&S[kk * LDT + row] = r[e];
@@ -260,7 +270,7 @@ struct BfTile {
   // gets row row0 + l % 16, k = ks + 8 (l / 16) .. + 7.
   __device__ __forceinline__ static bf16x8_t frag(const bf16_t* S, int row0, int ks, int lane) {
     if (KC) {
-      return *(const bf16x8_t*)&S[(row0 + (lane & 15)) * BLDK + ks + 8 * (lane >> 4)];
+      return *(const bf16x8_t*)&S[kc_off(row0 + (lane & 15), ks + 8 * (lane >> 4))];
     } else {
       const int s = lane & 15;
       const bf16_t* p = &S[(ks + 8 * (lane >> 4) + (s >> 2)) * LDT + row0 + 4 * (s & 3)];
@@ -280,7 +290,7 @@ template <> __device__ __forceinline__ bf16_t to_out<bf16_t>(float v) { return f
 template <> __device__ __forceinline__ double to_out<double>(float v) { return (double)v; }
 
 template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT>
-__global__ __launch_bounds__(256, BBK == BBK_LONG ? 2 : ((AK && BKC) ? 4 : 3))
+__global__ __launch_bounds__(256, BBK == BBK_LONG ? 2 : ((AK && BKC && sizeof(OutT) <= 4) ? 4 : 3))
 void gemm_bf16_kernel(const KArgs a) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
@@ -346,7 +356,7 @@ void gemm_bf16_kernel(const KArgs a) {
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
     }
     if (kt + 1 < nk) {
       TA::store(ra, As + (cur ^ 1) * AS, tid);
@@ -355,25 +365,29 @@ void gemm_bf16_kernel(const KArgs a) {
     __syncthreads();
   }
 
-  // v_mfma_f32_16x16x32_bf16 result layout: element (i, j) of the 16 x 16 tile
-  // is register i % 4 of lane j + 16 (i / 4).
+  // The products are formed as C^T = B^T A^T (B fragment first): element (m, n)
+  // of a 16 x 16 block is register n % 4 of lane m + 16 (n / 4), so each lane
+  // holds four consecutive columns of one row.
   if constexpr (STAGE) {
     // Stage the tile through LDS (the K-loop buffers are free after the last
     // barrier) and write whole 16-byte row chunks.
     const bool part = a.splits > 1;
+    const int lr = lane & 15, lc = 4 * (lane >> 4);
     if (!part && sizeof(OutT) == 2) {
       bf16_t* Cs = (bf16_t*)smem;
       const float alpha = (float)a.alpha;
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int lm = wm * WM + i * 16 + 4 * (lane >> 4) + r;
-            const int ln = wn * WN + j * 16 + (lane & 15);
-            Cs[lm * LDC2 + ln] = f32_to_bf16(alpha * acc[i][j][r]);
-          }
+        for (int j = 0; j < TN; ++j) {
+          const int lm = wm * WM + i * 16 + lr;
+          const int ln = wn * WN + j * 16 + lc;
+          const uint32_t w0 = (uint32_t)f32_to_bf16(alpha * acc[i][j][0]) |
+                              ((uint32_t)f32_to_bf16(alpha * acc[i][j][1]) << 16);
+          const uint32_t w1 = (uint32_t)f32_to_bf16(alpha * acc[i][j][2]) |
+                              ((uint32_t)f32_to_bf16(alpha * acc[i][j][3]) << 16);
+          *(uint2*)&Cs[lm * LDC2 + ln] = make_uint2(w0, w1);
+        }
       __syncthreads();
       constexpr int EPC = 8, CPR = BN / EPC;
       bf16_t* dst = (bf16_t*)a.C + tc.b * a.scb;
@@ -402,13 +416,11 @@ void gemm_bf16_kernel(const KArgs a) {
 #pragma unroll
           for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
-#pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int lm = i * 16 + 4 * (lane >> 4) + r;
-                const int ln = wn * WN + j * 16 + (lane & 15);
-                Cs[lm * LDC4 + ln] = alpha * acc[i][j][r];
-              }
+            for (int j = 0; j < TN; ++j) {
+              const int lm = i * 16 + lr;
+              const int ln = wn * WN + j * 16 + lc;
+              *(f4_t*)&Cs[lm * LDC4 + ln] = alpha * acc[i][j];
+            }
         }
         __syncthreads();
         for (int c = tid; c < (BM / 2) * CPR; c += 256) {
@@ -432,8 +444,8 @@ void gemm_bf16_kernel(const KArgs a) {
       for (int j = 0; j < TN; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t gm = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
-          const int64_t gn = n0 + wn * WN + j * 16 + (lane & 15);
+          const int64_t gm = m0 + wm * WM + i * 16 + (lane & 15);
+          const int64_t gn = n0 + wn * WN + j * 16 + 4 * (lane >> 4) + r;
           if (gm < a.M && gn < a.N) store_out<OutT>(a, tc, gm, gn, (double)acc[i][j][r]);
         }
   }

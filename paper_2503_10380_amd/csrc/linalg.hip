@@ -13,12 +13,16 @@
 // step instead of once per work-group.  The first pivot is inverted by a
 // one-group launch of its own.
 //
-// The 64 x 64 pivot inverse runs in registers: four 16-wide block sweeps, each
-// with the 16 x 16 pivot block inverted inside one wave (readlane / DPP /
-// bpermute, reciprocal refined by Newton steps) and the rank-16 update on the
-// f64 matrix cores.  Symmetry is used throughout: the pivot column panel is
-// the transposed pivot row panel, and D times the pivot rows is the transposed
-// column panel times D.
+// The 64 x 64 pivot inverse runs in registers, each wave holding a slab of
+// 16 rows in the f64 matrix-core result layout, as four 16-wide block sweeps.
+// The wave that owns a panel's rows inverts its 16 x 16 pivot block in place
+// (pivot by readlane, pivot column by a DPP row broadcast, pivot row by one
+// 64-bit bpermute, reciprocal refined by Newton steps) and publishes the
+// inverse and its rows; the other waves form their column-panel products and
+// rank-16 updates on the matrix cores with operands taken from registers (the
+// matrix is symmetric, so the published pivot rows also give the pivot
+// columns).  The owner of the next panel updates its rows first and starts the
+// next pivot inverse while the others finish, so a panel needs one barrier.
 #include "linalg.h"
 
 #include <utility>
@@ -32,9 +36,12 @@ constexpr int LD = NB + 1;
 constexpr int PW = 16;  // panel width of the blocked pivot inverse
 constexpr int KS = NB / 4;  // k-steps of a 64-deep f64 MFMA product
 
-// LDS scratch of the pivot inverse: two pivot-row panels (PW x LD), two
-// column-panel products (NB x 17) and the 16 x 16 pivot inverse (PW x 17).
-constexpr int GJ_SCRATCH = 2 * PW * LD + 2 * NB * 17 + PW * 17;
+// LDS scratch of the pivot inverse: the published pivot rows (16 x LDR) and
+// pivot inverse (16 x 16) of two consecutive panels; also used to move a
+// register tile into the slab layout (NB x LD).
+constexpr int LDR = NB + 16;
+constexpr int GJ_PANEL = PW * LDR + PW * PW;
+constexpr int GJ_SCRATCH = (2 * GJ_PANEL > NB * LD) ? 2 * GJ_PANEL : NB * LD;
 constexpr int T1_SIZE = NB * LD > GJ_SCRATCH ? NB * LD : GJ_SCRATCH;
 
 // Register tiles use the v_mfma_f64_16x16x4f64 accumulator layout: wave w owns
@@ -112,15 +119,6 @@ __device__ __forceinline__ double readlane_f64(double x, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Value of lane (4 (lane / 4) + Q): a broadcast inside each group of four lanes.
-template <int Q>
-__device__ __forceinline__ double quad_bcast_f64(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_mov_dpp((int)b, Q * 0x55, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), Q * 0x55, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // 1 / p from the hardware estimate and two Newton-Raphson steps
 // (r <- r + r (1 - p r)); each step squares the relative error.
 __device__ __forceinline__ double recip_nr(double p) {
@@ -131,113 +129,147 @@ __device__ __forceinline__ double recip_nr(double p) {
   return fma(r, e, r);
 }
 
-// In-wave Gauss-Jordan inverse of a 16 x 16 SPD block held 4 elements per
-// lane: lane l holds row l / 4, columns 4 (l % 4) + c.  The pivot comes by
-// readlane, the pivot column by a DPP broadcast inside the lane's group of
-// four, the pivot row by bpermute; no LDS or barrier is involved.
-__device__ __forceinline__ bool gj16_wave(double (&g)[4]) {
+// Value of lane 16 (lane / 16) + Q: a broadcast inside each row of 16 lanes.
+template <int Q>
+__device__ __forceinline__ double row_bcast_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x150 + Q, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + Q, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// In-wave Gauss-Jordan inverse (in place) of a 16 x 16 SPD block held in the
+// f64 matrix-core result layout: lane l holds column l % 16, rows 4 c + l / 16
+// in register c.  Pivot k sits in register k / 4 of lane 16 (k % 4) + k; the
+// pivot column at a lane's rows is in the same registers of lane 16 (l / 16) + k
+// (a broadcast inside each row of 16 lanes); the pivot row at a lane's column
+// is register k / 4 of lane 16 (k % 4) + l % 16.
+__device__ __forceinline__ bool gj16_block(d4_t& g) {
   const int lane = threadIdx.x & 63;
-  const int i = lane >> 2, q = lane & 3;
+  const int col = lane & 15, rq = lane >> 4;
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < PW; ++k) {
-    const int kc = k & 3, kl = k >> 2;
-    double p = readlane_f64(g[kc], 4 * k + kl);
+    const int kr = k >> 2, kq = k & 3;
+    double p = readlane_f64(g[kr], 16 * kq + k);
     const bool bad = !(p > 0.0) || !isfinite(p);
     ok = ok && !bad;
     if (bad) p = 1.0;
-    double rk[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) rk[c] = __shfl(g[c], 4 * k + q);
-    double ck;
-    switch (kl) {
-      case 0: ck = quad_bcast_f64<0>(g[kc]); break;
-      case 1: ck = quad_bcast_f64<1>(g[kc]); break;
-      case 2: ck = quad_bcast_f64<2>(g[kc]); break;
-      default: ck = quad_bcast_f64<3>(g[kc]); break;
-    }
-    const double inv = recip_nr(p);
-    const double colv = -ck * inv;
+    const double rk = __shfl(g[kr], 16 * kq + col);
+    double ck[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int j = 4 * q + c;
-      const double r = rk[c] * inv;
-      const double gen = fma(-ck, r, g[c]);
-      const double on_row = (j == k) ? inv : r;
-      const double off_row = (j == k) ? colv : gen;
-      g[c] = (i == k) ? on_row : off_row;
+      switch (k) {
+        case 0: ck[c] = row_bcast_f64<0>(g[c]); break;
+        case 1: ck[c] = row_bcast_f64<1>(g[c]); break;
+        case 2: ck[c] = row_bcast_f64<2>(g[c]); break;
+        case 3: ck[c] = row_bcast_f64<3>(g[c]); break;
+        case 4: ck[c] = row_bcast_f64<4>(g[c]); break;
+        case 5: ck[c] = row_bcast_f64<5>(g[c]); break;
+        case 6: ck[c] = row_bcast_f64<6>(g[c]); break;
+        case 7: ck[c] = row_bcast_f64<7>(g[c]); break;
+        case 8: ck[c] = row_bcast_f64<8>(g[c]); break;
+        case 9: ck[c] = row_bcast_f64<9>(g[c]); break;
+        case 10: ck[c] = row_bcast_f64<10>(g[c]); break;
+        case 11: ck[c] = row_bcast_f64<11>(g[c]); break;
+        case 12: ck[c] = row_bcast_f64<12>(g[c]); break;
+        case 13: ck[c] = row_bcast_f64<13>(g[c]); break;
+        case 14: ck[c] = row_bcast_f64<14>(g[c]); break;
+        default: ck[c] = row_bcast_f64<15>(g[c]); break;
+      }
+    }
+    const double inv = recip_nr(p);
+    const double r = rk * inv;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const bool on_row = (4 * c + rq) == k, on_col = col == k;
+      const double gen = fma(-ck[c], r, g[c]);
+      const double v_row = on_col ? inv : r;
+      const double v_off = on_col ? -ck[c] * inv : gen;
+      g[c] = on_row ? v_row : v_off;
     }
   }
   return ok;
 }
 
-// P <- P^{-1} for the NB x NB SPD tile P held in registers (RTile layout), by
-// four 16-wide block sweeps.  Per panel: the pivot rows go to LDS, wave 0
-// inverts the 16 x 16 pivot block, every wave forms its 16 rows of
-// Cp = P_{:,panel} D on the matrix cores (P_{:,panel} read as the transposed
-// row panel), and the rank-16 update P -= Cp P_{panel,:} runs on the matrix
-// cores; the row panel becomes Cp^T, the column panel Cp, the pivot block -D.
-// Panel buffers alternate, so a panel needs three barriers.  `ws` is LDS
-// scratch of GJ_SCRATCH doubles.  Returns false if a pivot was not positive.
-__device__ bool gj_inverse_regs(RTile& P, double* ws) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  double* Dp = ws + 2 * PW * LD + 2 * NB * 17;  // D (16 x 17)
+// A slab: wave w holds rows 16 w .. 16 w + 15 of an NB x NB tile as four
+// 16 x 16 blocks in the matrix-core result layout: block j, register r of lane
+// l is element (16 w + 4 r + l / 16, 16 j + l % 16).
+struct Slab {
+  d4_t b[NB / PW];
+};
+__device__ __forceinline__ int sl_row(int r) { return 16 * (threadIdx.x >> 6) + 4 * r + ((threadIdx.x & 63) >> 4); }
+__device__ __forceinline__ int sl_col(int j) { return 16 * j + (threadIdx.x & 15); }
+
+// P <- P^{-1} for the NB x NB SPD tile held as a slab, by four 16-wide block
+// sweeps (the sweeps leave -P^{-1}, negated at the end).  Panel p: wave p
+// inverts its diagonal block (D), publishes D and its other blocks (the pivot
+// rows), and replaces its blocks by -D and D P_pj; every other wave w forms
+// Cp = P_wp D and its transpose (P_wp read as the transposed pivot rows),
+// updates P_wj -= Cp P_pj and sets P_wp = Cp.  `ws` holds GJ_SCRATCH doubles.
+// Returns false (in the wave that met it) if a pivot was not positive.
+__device__ bool gj_inverse_slab(Slab& P, double* ws) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane >> 4, lc = lane & 15;
   bool ok = true;
 #pragma unroll
-  for (int pnl = 0; pnl < NB / PW; ++pnl) {
-    const int q0 = pnl * PW;
-    double* Rp = ws + (pnl & 1) * PW * LD;                 // pivot rows (16 x LD)
-    double* Cp = ws + 2 * PW * LD + (pnl & 1) * NB * 17;  // P_{:,panel} D (NB x 17)
+  for (int p = 0; p < NB / PW; ++p) {
+    double* Rp = ws + (p & 1) * GJ_PANEL;  // pivot rows (PW x LDR)
+    double* Dp = Rp + PW * LDR;           // pivot inverse (PW x PW)
+    d4_t dreg;
+    if (wave == p) {
+      ok = gj16_block(P.b[p]) && ok;
+      dreg = P.b[p];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int r = 0; r < 4; ++r) {
+        Dp[(4 * r + lr) * PW + lc] = dreg[r];
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = rt_row(i, r);
-          if (row >= q0 && row < q0 + PW) Rp[(row - q0) * LD + rt_col(j)] = P.v[i][j][r];
-        }
-    __syncthreads();
-    if (wave == 0) {
-      double g[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) g[c] = Rp[(lane >> 2) * LD + q0 + 4 * (lane & 3) + c];
-      ok = gj16_wave(g) && ok;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) Dp[(lane >> 2) * 17 + 4 * (lane & 3) + c] = g[c];
-    }
-    __syncthreads();
-    {  // rows 16 wave .. 16 wave + 15 of Cp: A(m, k) = Rp[k][16 wave + m], B(k, n) = D[k][n]
-      d4_t c = d4_t{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < PW / 4; ++s) {
-        const double a = Rp[(4 * s + (lane >> 4)) * LD + 16 * wave + (lane & 15)];
-        const double b = Dp[(4 * s + (lane >> 4)) * 17 + (lane & 15)];
-        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+        for (int j = 0; j < NB / PW; ++j)
+          if (j != p) Rp[(4 * r + lr) * LDR + 16 * j + lc] = P.b[j][r];
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Cp[(16 * wave + 4 * r + (lane >> 4)) * 17 + (lane & 15)] = c[r];
     }
     __syncthreads();
-    mfma_mm<PW, true>(Cp, 17, Rp, LD, P);  // P -= Cp Rp
+    if (wave == p) {  // own rows: P_pj <- D P_pj, P_pp <- -D
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < NB / PW; ++j) {
+        if (j == p) continue;
+        d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+        for (int s2 = 0; s2 < 4; ++s2)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(dreg[s2], P.b[j][s2], acc, 0, 0, 0);
+        P.b[j] = acc;
+      }
+      P.b[p] = -dreg;
+    } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = rt_row(i, r), col = rt_col(j);
-          const bool ip = row >= q0 && row < q0 + PW, jp = col >= q0 && col < q0 + PW;
-          if (ip && jp) P.v[i][j][r] = -Dp[(row - q0) * 17 + (col - q0)];
-          else if (ip) P.v[i][j][r] = Cp[col * 17 + (row - q0)];
-          else if (jp) P.v[i][j][r] = Cp[row * 17 + (col - q0)];
-        }
+      for (int r = 0; r < 4; ++r) dreg[r] = Dp[(4 * r + lr) * PW + lc];
+      double rw[4];  // P_pw (= P_wp^T) in B / A operand layout
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) rw[s2] = Rp[(4 * s2 + lr) * LDR + 16 * wave + lc];
+      d4_t cp = d4_t{0.0, 0.0, 0.0, 0.0}, cpt = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        cp = __builtin_amdgcn_mfma_f64_16x16x4f64(rw[s2], dreg[s2], cp, 0, 0, 0);    // P_wp D
+        cpt = __builtin_amdgcn_mfma_f64_16x16x4f64(dreg[s2], rw[s2], cpt, 0, 0, 0);  // D P_pw
+      }
+      // the next pivot's block first, so its inverse can start at once
+      constexpr int order[4][4] = {{1, 2, 3, 0}, {2, 3, 0, 1}, {3, 0, 1, 2}, {0, 1, 2, 3}};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = order[p][t];
+        if (j == p) continue;
+        double rj[4];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) rj[s2] = Rp[(4 * s2 + lr) * LDR + 16 * j + lc];
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+          P.b[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-cpt[s2], rj[s2], P.b[j], 0, 0, 0);
+      }
+      P.b[p] = cp;
+    }
   }
-  // the sweeps leave -P^{-1}
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) P.v[i][j] = -P.v[i][j];
+  for (int j = 0; j < NB / PW; ++j) P.b[j] = -P.b[j];
   return ok;
 }
 
@@ -266,6 +298,13 @@ __device__ __forceinline__ void rt_store(const RTile& t, double* O, int64_t ld, 
       }
 }
 
+__device__ __forceinline__ void slab_store(const Slab& t, double* O) {
+#pragma unroll
+  for (int j = 0; j < NB / PW; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) O[sl_row(r) * NB + sl_col(j)] = t.b[j][r];
+}
+
 // Inverts diagonal block 0 of A (n = min(NB, R) rows) into Dout (NB x NB,
 // identity-padded).
 __global__ __launch_bounds__(256) void first_pivot_kernel(const double* __restrict__ A,
@@ -273,26 +312,23 @@ __global__ __launch_bounds__(256) void first_pivot_kernel(const double* __restri
                                                           int* status) {
   __shared__ double ws[GJ_SCRATCH];
   const int n = (int)min((int64_t)NB, R);
-  RTile p;
+  Slab p;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < NB / PW; ++j)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rt_row(i, r), col = rt_col(j);
-        p.v[i][j][r] = (row < n && col < n) ? A[row * R + col] : 0.0;
-      }
-  rt_pad_identity(p, n);
-  const bool ok = gj_inverse_regs(p, ws);
-  if (!ok && threadIdx.x == 0) status[0] = 1;
-  rt_store(p, Dout, NB, NB, NB);
+    for (int r = 0; r < 4; ++r) {
+      const int row = sl_row(r), col = sl_col(j);
+      p.b[j][r] = (row < n && col < n) ? A[row * R + col] : (row == col ? 1.0 : 0.0);
+    }
+  const bool ok = gj_inverse_slab(p, ws);
+  if (!ok && (threadIdx.x & 63) == 0) status[0] = 1;
+  slab_store(p, Dout);
 }
 
 // One block step of the sweep; Dk = A_kk^{-1} (NB x NB) comes from the previous
 // launch.  The group whose output is diagonal block k + 1 also inverts that
 // block into Dnext.
-__global__ __launch_bounds__(256) void sweep_kernel(const double* __restrict__ A,
+__global__ __launch_bounds__(256, 2) void sweep_kernel(const double* __restrict__ A,
                                                     double* __restrict__ O,
                                                     const double* __restrict__ Dk,
                                                     double* __restrict__ Dnext, int64_t R,
@@ -380,11 +416,24 @@ __global__ __launch_bounds__(256) void sweep_kernel(const double* __restrict__ A
   rt_store(out, O + i0 * R + j0, R, ni, nj);
 
   if (I == kb + 1 && J == kb + 1) {  // look ahead: invert the next pivot block
-    __syncthreads();                 // T1 is free for the inverse's scratch
+    __syncthreads();                 // T1 is free: move the tile into the slab layout
     rt_pad_identity(out, ni);
-    const bool ok = gj_inverse_regs(out, T1);
-    if (!ok && tid == 0) status[0] = 1;
-    rt_store(out, Dnext, NB, NB, NB);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) T1[rt_row(i, r) * LD + rt_col(j)] = out.v[i][j][r];
+    __syncthreads();
+    Slab piv;
+#pragma unroll
+    for (int j = 0; j < NB / PW; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) piv.b[j][r] = T1[sl_row(r) * LD + sl_col(j)];
+    __syncthreads();  // T1 becomes the inverse's scratch
+    const bool ok = gj_inverse_slab(piv, T1);
+    if (!ok && lane == 0) status[0] = 1;
+    slab_store(piv, Dnext);
   }
 }
 
