@@ -41,7 +41,7 @@ constexpr int KS = NB / 4;  // k-steps of a 64-deep f64 MFMA product
 // register tile into the slab layout (NB x LD).
 constexpr int LDR = NB + 16;
 constexpr int GJ_PANEL = PW * LDR + PW * PW;
-constexpr int GJ_SCRATCH = (2 * GJ_PANEL > NB * LD) ? 2 * GJ_PANEL : NB * LD;
+constexpr int GJ_SCRATCH = (2 * GJ_PANEL + NB > NB * LD) ? 2 * GJ_PANEL + NB : NB * LD;
 constexpr int T1_SIZE = NB * LD > GJ_SCRATCH ? NB * LD : GJ_SCRATCH;
 
 // Register tiles use the v_mfma_f64_16x16x4f64 accumulator layout: wave w owns
@@ -138,12 +138,26 @@ __device__ __forceinline__ double row_bcast_f64(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// 1 / sqrt(d) from the hardware estimate and two Newton-Raphson steps
+// (y <- y (3 - d y^2) / 2); each step squares the relative error.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-0.5 * d, y * y, 1.5);
+  return y * fma(-0.5 * d, y * y, 1.5);
+}
+
 // In-wave Gauss-Jordan inverse (in place) of a 16 x 16 SPD block held in the
 // f64 matrix-core result layout: lane l holds column l % 16, rows 4 c + l / 16
 // in register c.  Pivot k sits in register k / 4 of lane 16 (k % 4) + k; the
 // pivot column at a lane's rows is in the same registers of lane 16 (l / 16) + k
 // (a broadcast inside each row of 16 lanes); the pivot row at a lane's column
 // is register k / 4 of lane 16 (k % 4) + l % 16.
+//
+// Each pivot step is one rank-1 update g_ij -= c_i r_j with
+// r_j = (g_kj + [j = k]) / p and c_i = g_ik - [i = k]: for i, j != k this is the
+// elimination g_ij - g_ik g_kj / p, and it also turns the pivot row into
+// g_kj / p, the pivot column into -g_ik / p and the pivot into 1 / p, so no
+// entry needs a case of its own.
 __device__ __forceinline__ bool gj16_block(d4_t& g) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, rq = lane >> 4;
@@ -179,15 +193,10 @@ __device__ __forceinline__ bool gj16_block(d4_t& g) {
       }
     }
     const double inv = recip_nr(p);
-    const double r = rk * inv;
+    const double r = (rk + (col == k ? 1.0 : 0.0)) * inv;
+    ck[kr] -= (rq == kq) ? 1.0 : 0.0;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const bool on_row = (4 * c + rq) == k, on_col = col == k;
-      const double gen = fma(-ck[c], r, g[c]);
-      const double v_row = on_col ? inv : r;
-      const double v_off = on_col ? -ck[c] * inv : gen;
-      g[c] = on_row ? v_row : v_off;
-    }
+    for (int c = 0; c < 4; ++c) g[c] = fma(-ck[c], r, g[c]);
   }
   return ok;
 }
@@ -201,8 +210,13 @@ struct Slab {
 __device__ __forceinline__ int sl_row(int r) { return 16 * (threadIdx.x >> 6) + 4 * r + ((threadIdx.x & 63) >> 4); }
 __device__ __forceinline__ int sl_col(int j) { return 16 * j + (threadIdx.x & 15); }
 
-// P <- P^{-1} for the NB x NB SPD tile held as a slab, by four 16-wide block
-// sweeps (the sweeps leave -P^{-1}, negated at the end).  Panel p: wave p
+// P <- P^{-1} for the NB x NB SPD tile held as a slab.  The tile is first
+// scaled to unit diagonal, S P S with S = diag(P)^{-1/2}, so that every pivot
+// met afterwards (a Schur complement of a unit-diagonal SPD matrix) is at most
+// 1, where the uniform pivot step of gj16_block loses no precision; the result
+// is scaled back, P^{-1} = S (S P S)^{-1} S.  A diagonal entry that is <= 0 or
+// not finite counts as a bad pivot and is replaced by 1.  Then four 16-wide
+// block sweeps (they leave -P^{-1}, negated at the end).  Panel p: wave p
 // inverts its diagonal block (D), publishes D and its other blocks (the pivot
 // rows), and replaces its blocks by -D and D P_pj; every other wave w forms
 // Cp = P_wp D and its transpose (P_wp read as the transposed pivot rows),
@@ -212,6 +226,33 @@ __device__ bool gj_inverse_slab(Slab& P, double* ws) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lr = lane >> 4, lc = lane & 15;
   bool ok = true;
+  double* dg = ws + 2 * GJ_PANEL;  // the diagonal (NB)
+  {
+    // lanes whose column matches one of their rows hold a diagonal entry of block `wave`
+    const int q = lc >> 2;
+#pragma unroll
+    for (int j = 0; j < NB / PW; ++j)
+      if (j == wave && (lc & 3) == lr)
+        dg[16 * j + lc] = q == 0 ? P.b[j][0] : (q == 1 ? P.b[j][1] : (q == 2 ? P.b[j][2] : P.b[j][3]));
+  }
+  __syncthreads();
+  double sr[4], sc[NB / PW];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double d = dg[16 * wave + 4 * r + lr];
+    if (!(d > 0.0) || !isfinite(d)) { ok = false; d = 1.0; }
+    sr[r] = rsqrt_nr(d);
+  }
+#pragma unroll
+  for (int j = 0; j < NB / PW; ++j) {
+    double d = dg[16 * j + lc];
+    if (!(d > 0.0) || !isfinite(d)) d = 1.0;
+    sc[j] = rsqrt_nr(d);
+  }
+#pragma unroll
+  for (int j = 0; j < NB / PW; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) P.b[j][r] *= sr[r] * sc[j];
 #pragma unroll
   for (int p = 0; p < NB / PW; ++p) {
     double* Rp = ws + (p & 1) * GJ_PANEL;  // pivot rows (PW x LDR)
@@ -269,7 +310,9 @@ __device__ bool gj_inverse_slab(Slab& P, double* ws) {
     }
   }
 #pragma unroll
-  for (int j = 0; j < NB / PW; ++j) P.b[j] = -P.b[j];
+  for (int j = 0; j < NB / PW; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) P.b[j][r] *= -(sr[r] * sc[j]);
   return ok;
 }
 
