@@ -73,6 +73,12 @@ typedef struct {
   int history_cap;       /* entries available in the report's history arrays */
   int energy;            /* non-zero: compute E_CP = sum R~ t after the last sweep */
   int timing;            /* non-zero: time kernel classes with HIP events */
+  double refine_tol;     /* > 0: the FP64 refinement stops once |fit_n - fit_{n-1}| < refine_tol,
+                            the first refinement sweep compared with the last BF16 one (at
+                            most refine_fp64_sweeps sweeps); 0: run them all */
+  int stop_window;       /* stop rule 1 on the main sweeps: compare |fit_n - fit_{n-w}| / w with
+                            tol, w = stop_window (1..64; 0 means 1), to average out the
+                            evaluation noise of BF16 fits */
 } cpppl_als_opts;
 
 /* Kernel classes timed when opts.timing is set (index into ms_class / n_class). */
@@ -104,6 +110,7 @@ typedef struct {
   double* fit_hist;      /* caller-owned, history_cap entries, or NULL */
   double* eta_hist;      /* caller-owned, history_cap entries, or NULL */
   double* ms_hist;       /* caller-owned, per-sweep milliseconds, or NULL */
+  int refine_done;       /* of sweeps_done, the FP64 refinement sweeps */
 } cpppl_als_report;
 
 /* ---- lifecycle ----------------------------------------------------------- */

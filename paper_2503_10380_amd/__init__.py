@@ -39,7 +39,7 @@ class Dims(C.Structure):
 class AlsOpts(C.Structure):
     _fields_ = [("max_sweeps", C.c_int), ("stop_rule", C.c_int), ("tol", C.c_double),
                 ("refine_fp64_sweeps", C.c_int), ("history_cap", C.c_int), ("energy", C.c_int),
-                ("timing", C.c_int)]
+                ("timing", C.c_int), ("refine_tol", C.c_double), ("stop_window", C.c_int)]
 
 
 class AlsReport(C.Structure):
@@ -48,7 +48,7 @@ class AlsReport(C.Structure):
                 ("eta", C.c_double), ("energy_cp", C.c_double), ("ms_total", C.c_double),
                 ("ms_class", C.c_double * 16), ("n_class", C.c_int * 16),
                 ("fit_hist", C.POINTER(C.c_double)), ("eta_hist", C.POINTER(C.c_double)),
-                ("ms_hist", C.POINTER(C.c_double))]
+                ("ms_hist", C.POINTER(C.c_double)), ("refine_done", C.c_int)]
 
 
 _lib = None
@@ -247,12 +247,14 @@ class Context:
         return (*out, lam)
 
     # ------------------------------------------------------------------ work
-    def als(self, sweeps, stop_rule=0, tol=0.0, refine=0, energy=False, timing=False):
+    def als(self, sweeps, stop_rule=0, tol=0.0, refine=0, energy=False, timing=False,
+            refine_tol=0.0, stop_window=1):
         cap = sweeps + refine
         fit = np.full(cap, np.nan)
         eta = np.full(cap, np.nan)
         ms = np.full(cap, np.nan)
-        opts = AlsOpts(sweeps, stop_rule, tol, refine, cap, int(bool(energy)), int(bool(timing)))
+        opts = AlsOpts(sweeps, stop_rule, tol, refine, cap, int(bool(energy)), int(bool(timing)),
+                       refine_tol, stop_window)
         rep = AlsReport()
         rep.fit_hist = fit.ctypes.data_as(_D)
         rep.eta_hist = eta.ctypes.data_as(_D)
@@ -260,7 +262,8 @@ class Context:
         self._call("cpppl_als", C.byref(opts), C.byref(rep))
         n = rep.sweeps_done
         return {
-            "sweeps": n, "ridge_retries": rep.ridge_retries, "fit": rep.fit, "loss": rep.loss,
+            "sweeps": n, "refine_sweeps": rep.refine_done, "ridge_retries": rep.ridge_retries,
+            "fit": rep.fit, "loss": rep.loss,
             "inner": rep.inner, "cp_norm2": rep.cp_norm2, "eta": rep.eta,
             "energy_cp": rep.energy_cp, "ms_total": rep.ms_total,
             "ms_class": {k: rep.ms_class[i] for i, k in enumerate(T_CLASSES)},

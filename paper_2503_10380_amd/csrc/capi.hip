@@ -1029,6 +1029,10 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
   if (!opts || !rep) throw std::invalid_argument("opts/report is NULL");
   if (opts->max_sweeps < 0 || opts->refine_fp64_sweeps < 0) throw std::invalid_argument("negative sweep count");
   if (opts->stop_rule < 0 || opts->stop_rule > 2) throw std::invalid_argument("stop_rule must be 0, 1 or 2");
+  if (!(opts->refine_tol >= 0.0)) throw std::invalid_argument("refine_tol must be >= 0");
+  if (opts->stop_window < 0 || opts->stop_window > 64) throw std::invalid_argument("stop_window must be 0..64");
+  const int win = opts->stop_window > 1 ? opts->stop_window : 1;
+  std::vector<double> main_fits;
   require_inputs(c);
   ensure_norm(c);
   const Plan& p = c->plan;
@@ -1036,6 +1040,7 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
   c->ev_used = 0;
   c->segs.clear();
   rep->sweeps_done = 0;
+  rep->refine_done = 0;
   rep->ridge_retries = 0;
   rep->energy_cp = std::numeric_limits<double>::quiet_NaN();
   for (int k = 0; k < 16; ++k) { rep->ms_class[k] = 0.0; rep->n_class[k] = 0; }
@@ -1076,14 +1081,22 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
     if (rep->eta_hist && rep->sweeps_done < opts->history_cap) rep->eta_hist[rep->sweeps_done] = eta;
     if (rep->ms_hist && rep->sweeps_done < opts->history_cap) rep->ms_hist[rep->sweeps_done] = ms;
     rep->sweeps_done++;
+    if (refining) rep->refine_done++;
     rep->fit = fit;
     rep->eta = eta;
     rep->inner = c->host_scal[S_FIT + 0];
     rep->cp_norm2 = c->host_scal[S_FIT + 1];
     rep->loss = c->host_scal[S_FIT + 4];
     if (!refining) {
-      if (opts->stop_rule == 1 && std::isfinite(prev_fit) && std::fabs(fit - prev_fit) < opts->tol) stop_main = true;
+      main_fits.push_back(fit);
+      const size_t nf = main_fits.size();
+      if (opts->stop_rule == 1 && nf > (size_t)win &&
+          std::fabs(fit - main_fits[nf - 1 - win]) / win < opts->tol)
+        stop_main = true;
       if (opts->stop_rule == 2 && eta < opts->tol) stop_main = true;
+    } else if (opts->refine_tol > 0.0 && std::fabs(fit - prev_fit) < opts->refine_tol) {
+      prev_fit = fit;
+      break;
     }
     prev_fit = fit;
   }

@@ -223,3 +223,55 @@ def test_full_size_rank1_t2_closed_form(lib, cfg_name):
             assert err <= tol
         ctx.close()
         del ctx
+
+
+def test_fp64_refinement_matches_fp64_context(lib):
+    """FP64 refinement sweeps of a BF16 context are plain FP64 sweeps: from the
+    same factors they give what an FP64 context gives, and refine_tol stops
+    them once the fit changes by less than the tolerance."""
+    cfg = SMALL["ragged_tiles"]
+    _say("refinement = FP64 sweeps")
+    inp = synth.make_inputs(cfg)
+    c16 = _ctx(lib, cfg, inp, "bf16")
+    c16.set_factors(*synth.init_factors(cfg))
+    c16.als(3)
+    state = c16.get_factors()
+    r16 = c16.als(0, refine=2)
+    assert r16["sweeps"] == 2 and r16["refine_sweeps"] == 2
+    c64 = _ctx(lib, cfg, inp, "fp64")
+    c64.set_factors(*state)
+    r64 = c64.als(2)
+    np.testing.assert_allclose(r16["fit_hist"], r64["fit_hist"], rtol=0, atol=1e-12)
+    for a, b in zip(c16.get_factors(), c64.get_factors()):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-10 * max(1.0, np.abs(b).max()))
+    # BF16 sweeps to a stop rule, then refinement until |dfit| < 1e-4 (at most 40)
+    c16.set_factors(*state)
+    r = c16.als(20, stop_rule=1, tol=1e-3, refine=40, refine_tol=1e-4)
+    n_bf = r["sweeps"] - r["refine_sweeps"]
+    assert 1 <= n_bf <= 20 and 1 <= r["refine_sweeps"] <= 40
+    h = r["fit_hist"]
+    if r["refine_sweeps"] < 40:
+        assert abs(h[-1] - h[-2]) < 1e-4
+    if r["refine_sweeps"] > 1:
+        assert all(abs(h[k] - h[k - 1]) >= 1e-4 for k in range(n_bf, len(h) - 1))
+
+
+def test_windowed_stop_rule(lib):
+    """stop_window w: the main sweeps stop at the first n with
+    |fit_n - fit_{n-w}| / w < tol, checked on the returned history."""
+    cfg = SMALL["ragged_tiles"]
+    _say("windowed stop rule")
+    inp = synth.make_inputs(cfg)
+    ctx = _ctx(lib, cfg, inp, "fp64")
+    fs = synth.init_factors(cfg)
+    ctx.set_factors(*fs)
+    full = ctx.als(60)["fit_hist"]
+    w, tol = 4, 2e-3
+    want = next((n for n in range(w, 60) if abs(full[n] - full[n - w]) / w < tol), None)
+    ctx.set_factors(*fs)
+    r = ctx.als(60, stop_rule=1, tol=tol, stop_window=w)
+    if want is None:
+        assert r["sweeps"] == 60
+    else:
+        assert r["sweeps"] == want + 1
+        np.testing.assert_allclose(r["fit_hist"], full[:want + 1], rtol=0, atol=1e-12)
