@@ -246,6 +246,90 @@ def time_to_fit(cp, torch, cfg, inp, fs, dev_t, dev_b, args):
     return res
 
 
+def warmstart_experiment(cp, torch, args):
+    """Learned vs plain vs first-order warm start over a CCSD-like amplitude
+    sequence (C4 by default): t^(k+1) = t^(k) + 0.3^(k mod 10) eps_k, 20 steps.
+    Steps 1-10 train the per-column network on rows the GPU ALS generates
+    (plain warm start, then FP64 ALS to |dfit| < 1e-6); steps 11-20 start every
+    strategy from the same converged factors and run 30 FP64 sweeps, so every
+    fit is evaluated exactly.  Reported per strategy: the candidate the judge
+    kept, the fit of the warm start itself, fits after 1, 2 and 5 sweeps, and
+    sweeps until |dfit| < 1e-4 and < 1e-6 (the warm start's own fit counting as
+    sweep 0)."""
+    cfg = synth.CONFIGS[args.config]
+    inp = synth.make_inputs(cfg)
+    dev_b = torch.tensor(inp.b_vv, device="cuda")
+    ctx = cp.Context(cfg.o, cfg.v, cfg.nx, cfg.rank, "fp64")
+    ctx.load_t2(torch.tensor(inp.t, device="cuda"))
+    ctx.load_df(dev_b)
+    ctx.set_factors(*synth.init_factors(cfg))
+    t0 = time.perf_counter()
+    r0 = ctx.als(600, stop_rule=1, tol=1e-6)
+    net = cp.MLP(ctx.ws_in_dim, ctx.ws_out_dim, hidden=256, n_hidden=2,
+                 capacity=10 * cfg.rank, seed=7)
+    ts = [inp.t] + list(synth.amplitude_sequence(cfg, inp.t, 20, period=10))
+    strategies = (("plain", cp.WS_PLAIN), ("first_order", cp.WS_FIRST_ORDER),
+                  ("learned", cp.WS_LEARNED))
+
+    def converge_plain(k):
+        ctx.load_t2(torch.tensor(ts[k - 1], device="cuda"))
+        ctx.set_factors(*state)
+        ctx.warm_start(ts[k] - ts[k - 1], cp.WS_PLAIN)
+        return ctx.als(400, stop_rule=1, tol=1e-6)
+
+    state = ctx.get_factors()
+    train_sweeps = []
+    for k in range(1, 11):
+        r = converge_plain(k)
+        train_sweeps.append(r["sweeps"])
+        ctx.training_rows(net)
+        state = ctx.get_factors()
+    t_train = time.perf_counter()
+    hist = net.train(args.ws_epochs, lr=1e-3, batch=512, seed=1)
+    t_train = time.perf_counter() - t_train
+    rows = []
+    for k in range(11, 21):
+        row = {}
+        for name, strat in strategies:
+            ctx.load_t2(torch.tensor(ts[k - 1], device="cuda"))
+            ctx.set_factors(*state)
+            chosen = ctx.warm_start(ts[k] - ts[k - 1], strat, net if strat == cp.WS_LEARNED else None)
+            f0 = ctx.fit()[0]
+            h = np.concatenate([[f0], ctx.als(30)["fit_hist"]])
+            d = np.abs(np.diff(h))
+            n4 = int(np.argmax(d < 1e-4)) + 1 if np.any(d < 1e-4) else None
+            n6 = int(np.argmax(d < 1e-6)) + 1 if np.any(d < 1e-6) else None
+            row[name] = {"chosen": int(chosen), "fit0": float(f0), "fit1": float(h[1]),
+                         "fit2": float(h[2]), "fit5": float(h[5]), "fit30": float(h[30]),
+                         "sweeps_to_dfit_1e-4": n4, "sweeps_to_dfit_1e-6": n6}
+        rows.append(row)
+        converge_plain(k)
+        state = ctx.get_factors()
+    summary = {}
+    for name, _ in strategies:
+        summary[name] = {
+            "chosen_non_plain": int(sum(r[name]["chosen"] != cp.WS_PLAIN for r in rows)),
+            "mean_fit0": float(np.mean([r[name]["fit0"] for r in rows])),
+            "mean_fit1": float(np.mean([r[name]["fit1"] for r in rows])),
+            "mean_fit5": float(np.mean([r[name]["fit5"] for r in rows])),
+            "mean_fit30": float(np.mean([r[name]["fit30"] for r in rows])),
+            "mean_sweeps_to_dfit_1e-4": float(np.mean([r[name]["sweeps_to_dfit_1e-4"] or 31
+                                                       for r in rows])),
+            "mean_sweeps_to_dfit_1e-6": float(np.mean([r[name]["sweeps_to_dfit_1e-6"] or 31
+                                                       for r in rows])),
+        }
+    ctx.close()
+    return {"metric": "warm start over an amplitude sequence: fit of the start and sweeps to "
+                      "|dfit|<1e-4, steps 11-20", "config": {"workload": cfg.name, "o": cfg.o,
+            "v": cfg.v, "nx": cfg.nx, "rank": cfg.rank, "als": "fp64"},
+            "step0": {"sweeps": r0["sweeps"], "fit": r0["fit"]},
+            "train": {"steps": 10, "sweeps_per_step": train_sweeps, "rows": net.num_rows,
+                      "epochs": args.ws_epochs, "loss_first": float(hist[0]),
+                      "loss_last": float(hist[-1]), "train_s": t_train},
+            "summary": summary, "steps": rows,
+            "wall_s": time.perf_counter() - t0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,6 +344,9 @@ def main():
                     help="cap on the sweeps of each time-to-fit run (and on the refinement)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--experiment", choices=["warmstart"],
+                    help="run the learned warm-start experiment (C4 unless --config) instead")
+    ap.add_argument("--ws-epochs", type=int, default=300)
     ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
                          "script into profiles/traffic_counters.json and exit")
@@ -267,6 +354,13 @@ def main():
                     help="first run three plain device copies of MIB MiB each, so that "
                          "HBM byte counters can be scaled against a kernel of known traffic")
     args = ap.parse_args()
+    if args.experiment == "warmstart":
+        import torch
+        import paper_2503_10380_amd as cp
+        if args.config == "C3":
+            args.config = "C4"
+        print(json.dumps(warmstart_experiment(cp, torch, args)))
+        return
     if args.digest_counters:
         digest_counters(args.digest_counters[0], args.digest_counters[1], args.steps,
                         args.copy_calibration, TRAFFIC_FILE)
