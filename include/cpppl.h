@@ -79,6 +79,8 @@ typedef struct {
   int stop_window;       /* stop rule 1 on the main sweeps: compare |fit_n - fit_{n-w}| / w with
                             tol, w = stop_window (1..64; 0 means 1), to average out the
                             evaluation noise of BF16 fits */
+  int eta;               /* non-zero: evaluate eta (eq. N3_stopping) after every sweep (implied
+                            by stop_rule 2); otherwise the report's eta values are NaN */
 } cpppl_als_opts;
 
 /* Kernel classes timed when opts.timing is set (index into ms_class / n_class). */

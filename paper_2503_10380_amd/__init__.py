@@ -39,7 +39,8 @@ class Dims(C.Structure):
 class AlsOpts(C.Structure):
     _fields_ = [("max_sweeps", C.c_int), ("stop_rule", C.c_int), ("tol", C.c_double),
                 ("refine_fp64_sweeps", C.c_int), ("history_cap", C.c_int), ("energy", C.c_int),
-                ("timing", C.c_int), ("refine_tol", C.c_double), ("stop_window", C.c_int)]
+                ("timing", C.c_int), ("refine_tol", C.c_double), ("stop_window", C.c_int),
+                ("eta", C.c_int)]
 
 
 class AlsReport(C.Structure):
@@ -248,16 +249,16 @@ class Context:
 
     # ------------------------------------------------------------------ work
     def als(self, sweeps, stop_rule=0, tol=0.0, refine=0, energy=False, timing=False,
-            refine_tol=0.0, stop_window=1):
+            refine_tol=0.0, stop_window=1, eta=False):
         cap = sweeps + refine
-        fit = np.full(cap, np.nan)
-        eta = np.full(cap, np.nan)
-        ms = np.full(cap, np.nan)
         opts = AlsOpts(sweeps, stop_rule, tol, refine, cap, int(bool(energy)), int(bool(timing)),
-                       refine_tol, stop_window)
+                       refine_tol, stop_window, int(bool(eta)))
+        fit = np.full(cap, np.nan)
+        eta_h = np.full(cap, np.nan)
+        ms = np.full(cap, np.nan)
         rep = AlsReport()
         rep.fit_hist = fit.ctypes.data_as(_D)
-        rep.eta_hist = eta.ctypes.data_as(_D)
+        rep.eta_hist = eta_h.ctypes.data_as(_D)
         rep.ms_hist = ms.ctypes.data_as(_D)
         self._call("cpppl_als", C.byref(opts), C.byref(rep))
         n = rep.sweeps_done
@@ -268,7 +269,7 @@ class Context:
             "energy_cp": rep.energy_cp, "ms_total": rep.ms_total,
             "ms_class": {k: rep.ms_class[i] for i, k in enumerate(T_CLASSES)},
             "n_class": {k: rep.n_class[i] for i, k in enumerate(T_CLASSES)},
-            "fit_hist": fit[:n].copy(), "eta_hist": eta[:n].copy(), "ms_hist": ms[:n].copy(),
+            "fit_hist": fit[:n].copy(), "eta_hist": eta_h[:n].copy(), "ms_hist": ms[:n].copy(),
         }
 
     def mttkrp(self, mode, precision=None):

@@ -106,7 +106,7 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   p.HT = add((size_t)(R * o * o) * 8);
   p.partial_elems = (size_t)std::max({64 * R * v, 16 * R * o * o, 4 * R * R, (int64_t)1 << 16});
   p.partial = add(p.partial_elems * 8);
-  p.rowbuf = add((size_t)std::max<int64_t>(R, 4096) * 8);
+  p.rowbuf = add((size_t)std::max<int64_t>(2 * R, 4096) * 8);
   p.sums = add(2 * 1024 * 8);
   p.scal = add(S_COUNT * 8);
   p.status = add(16 * 4);
@@ -398,9 +398,11 @@ int solve_mode(cpppl_ctx* c, int m, bool careful) {
   return r;
 }
 
-// Start -W_m^{-1} on the side stream once the main stream has produced the Grams it needs.
+// Marks the point of the main stream after which the Grams W_m needs are ready.
+void mark_fork(cpppl_ctx* c) { CPPPL_HIP(hipEventRecord(c->ev_main, c->stream)); }
+
+// Start -W_m^{-1} on the side stream from the point marked by mark_fork.
 void fork_inverse(cpppl_ctx* c, int m) {
-  CPPPL_HIP(hipEventRecord(c->ev_main, c->stream));
   CPPPL_HIP(hipStreamWaitEvent(c->side, c->ev_main, 0));
   prepare_inverse(c, m, c->side, false);
   CPPPL_HIP(hipEventRecord(c->ev_side, c->side));
@@ -458,8 +460,18 @@ void compute_eta(cpppl_ctx* c) {
 void snapshot(cpppl_ctx* c) {
   const Plan& p = c->plan;
   const int64_t R = c->d.rank;
-  for (int m = 0; m < 4; ++m) copy_d2d(c, p.FTprev[m], p.FT[m], (size_t)(nmode(c->d, m) * R) * 8);
-  copy_d2d(c, p.lamprev, p.lam, (size_t)R * 8);
+  const double* src[5];
+  double* dst[5];
+  int64_t n[5];
+  for (int m = 0; m < 4; ++m) {
+    src[m] = c->at<double>(p.FT[m]);
+    dst[m] = c->at<double>(p.FTprev[m]);
+    n[m] = nmode(c->d, m) * R;
+  }
+  src[4] = c->at<double>(p.lam);
+  dst[4] = c->at<double>(p.lamprev);
+  n[4] = R;
+  copy_doubles(src, dst, n, 5, c->stream);
 }
 
 void restore_snapshot(cpppl_ctx* c) {
@@ -515,21 +527,26 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful) {
       c->ybeta_dt = P.dt;
     }
   } else {
-    fork_inverse(c, 2);
+    // Each mode's first main-stream kernel is queued before the side stream's
+    // inverse launches, so the main queue never waits on the host issuing them.
+    mark_fork(c);
     compute_tau(c, P);
+    fork_inverse(c, 2);
     if (!c->ybeta_valid || c->ybeta_dt != P.dt) compute_Y(c, P, 3, p.Yb);
     compute_Z(c, P, 2);
     compute_M(c, P);
     join_inverse(c);
     apply_inverse(c, 2);
-    fork_inverse(c, 3);
+    mark_fork(c);
     compute_Y(c, P, 2, p.Ya);
+    fork_inverse(c, 3);
     compute_Z(c, P, 3);
     compute_M(c, P);
     join_inverse(c);
     apply_inverse(c, 3);
-    fork_inverse(c, 0);
+    mark_fork(c);
     compute_Y(c, P, 3, p.Yb);
+    fork_inverse(c, 0);
     c->ybeta_valid = true;
     c->ybeta_dt = P.dt;
     compute_G(c, P);
@@ -548,7 +565,12 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful) {
                 c->d.rank, c->at<double>(p.scal) + S_NORM_R2, c->at<double>(p.rowbuf),
                 c->at<double>(p.scal) + S_FIT, c->stream);
   }
-  compute_eta(c);
+  if (c->want_eta) {
+    compute_eta(c);
+  } else {  // keep ||CP||^2 as the reference of a later eta
+    double* sc = c->at<double>(p.scal);
+    CPPPL_HIP(hipMemcpyAsync(sc + S_CP2_PREV, sc + S_FIT + 1, 8, hipMemcpyDeviceToDevice, c->stream));
+  }
   return retries;
 }
 
@@ -1032,6 +1054,7 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
   if (!(opts->refine_tol >= 0.0)) throw std::invalid_argument("refine_tol must be >= 0");
   if (opts->stop_window < 0 || opts->stop_window > 64) throw std::invalid_argument("stop_window must be 0..64");
   const int win = opts->stop_window > 1 ? opts->stop_window : 1;
+  c->want_eta = opts->eta != 0 || opts->stop_rule == 2;
   std::vector<double> main_fits;
   require_inputs(c);
   ensure_norm(c);
@@ -1073,7 +1096,7 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
     }
     rep->ridge_retries += retries;
     const double fit = c->host_scal[S_FIT + 3];
-    const double eta = c->host_scal[S_ETA + 3];
+    const double eta = c->want_eta ? c->host_scal[S_ETA + 3] : std::numeric_limits<double>::quiet_NaN();
     if (!std::isfinite(fit) || !std::isfinite(c->host_scal[S_FIT + 1]))
       throw StatusError(CPPPL_E_NONFINITE, "non-finite fit after sweep " + std::to_string(s + 1));
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ts).count();

@@ -73,6 +73,7 @@ struct cpppl_ctx {
   int64_t rank_p = 0;
   bool norm_valid = false;
   bool ybeta_valid = false;
+  bool want_eta = true;  // sweeps evaluate eta (eq. N3_stopping)
   cpppl::DType ybeta_dt = cpppl::DType::F64;
   bool ws_valid = false;      // warm-start snapshot (wsF) holds the factors before the last warm start
 

@@ -38,10 +38,13 @@ void occ_reduce(const double* HT, const double* other, double* M, int64_t o, int
 //   sc[0] = <R, CP> = sum_r lam_r sum_n MT[r][n] FT[r][n]
 //   sc[1] = ||CP||^2 = lam^T (G0 .* G1 .* G2 .* G3) lam
 //   sc[2] = residual^2 = max(norm_r2 - 2 sc[0] + sc[1], 0), sc[3] = fit, sc[4] = loss
-// `rowbuf` holds R doubles of scratch; norm_r2 is read from device memory.
+// `rowbuf` holds 2R doubles of scratch; norm_r2 is read from device memory.
 void fit_scalars(const double* MT, const double* FT, int64_t n, const double* lam,
                  const double* const G[4], int64_t R, const double* norm_r2, double* rowbuf,
                  double* sc, hipStream_t s);
+// dst[q][0:n[q]] = src[q][0:n[q]] for q < count (1..5), one launch.
+void copy_doubles(const double* const* src, double* const* dst, const int64_t* n, int count,
+                  hipStream_t s);
 // out = lamA^T (X0 .* X1 .* X2 .* X3) lamB for R x R cross products (eta terms).
 void weighted_hadamard_sum(const double* const X[4], const double* lamA, const double* lamB,
                            int64_t R, double* rowbuf, double* out, hipStream_t s);

@@ -4,6 +4,7 @@
 #include "ops.h"
 
 #include <algorithm>
+#include <stdexcept>
 
 namespace cpppl {
 
@@ -156,20 +157,40 @@ __global__ __launch_bounds__(TPB) void weighted_rows_kernel(const double* X0, co
   if (threadIdx.x == 0) rowbuf[r] = lamA[r] * s;
 }
 
-__global__ __launch_bounds__(TPB) void fit_finish_kernel(const double* MT, const double* FT,
-                                                         int64_t n, const double* lam, int64_t R,
-                                                         const double* rowbuf,
+// Row r of the fit terms: rowbuf[r] = lam_r sum_c lam_c (G0 .* G1 .* G2 .* G3)_rc
+// (||CP||^2 by Grams) and rowbuf[R + r] = lam_r sum_k MT[r][k] FT[r][k] (<R, CP>
+// from the last mode's MTTKRP).
+__global__ __launch_bounds__(TPB) void fit_rows_kernel(const double* X0, const double* X1,
+                                                       const double* X2, const double* X3,
+                                                       const double* lam, const double* MT,
+                                                       const double* FT, int64_t n, int64_t R,
+                                                       double* rowbuf) {
+  __shared__ double sh[TPB];
+  const int64_t r = blockIdx.x;
+  double s = 0.0;
+  for (int64_t c = threadIdx.x; c < R; c += TPB) {
+    const int64_t i = r * R + c;
+    s += lam[c] * X0[i] * X1[i] * X2[i] * X3[i];
+  }
+  s = block_sum(s, sh);
+  double d = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += TPB) d += MT[r * n + k] * FT[r * n + k];
+  d = block_sum(d, sh);
+  if (threadIdx.x == 0) {
+    rowbuf[r] = lam[r] * s;
+    rowbuf[R + r] = lam[r] * d;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void fit_finish_kernel(int64_t R, const double* rowbuf,
                                                          const double* norm_r2, double* sc) {
   __shared__ double sh[TPB];
-  double cp = 0.0;
-  for (int64_t r = threadIdx.x; r < R; r += TPB) cp += rowbuf[r];
-  cp = block_sum(cp, sh);
-  double in = 0.0;
+  double cp = 0.0, in = 0.0;
   for (int64_t r = threadIdx.x; r < R; r += TPB) {
-    double d = 0.0;
-    for (int64_t k = 0; k < n; ++k) d += MT[r * n + k] * FT[r * n + k];
-    in += lam[r] * d;
+    cp += rowbuf[r];
+    in += rowbuf[R + r];
   }
+  cp = block_sum(cp, sh);
   in = block_sum(in, sh);
   if (threadIdx.x == 0) {
     const double n2 = *norm_r2;
@@ -181,6 +202,19 @@ __global__ __launch_bounds__(TPB) void fit_finish_kernel(const double* MT, const
     sc[3] = 1.0 - sqrt(res2) / sqrt(n2);
     sc[4] = 0.5 * res2;
   }
+}
+
+// Up to four (src, dst, count) copies of doubles in one launch.
+struct CopyList {
+  const double* src[5];
+  double* dst[5];
+  int64_t n[5];
+  int count;
+};
+__global__ __launch_bounds__(TPB) void copy_list_kernel(const CopyList L) {
+  for (int q = 0; q < L.count; ++q)
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < L.n[q]; i += (int64_t)gridDim.x * TPB)
+      L.dst[q][i] = L.src[q][i];
 }
 
 __global__ __launch_bounds__(TPB) void sum_rows_kernel(const double* rowbuf, int64_t R,
@@ -371,12 +405,28 @@ void occ_reduce(const double* HT, const double* other, double* M, int64_t o, int
 void fit_scalars(const double* MT, const double* FT, int64_t n, const double* lam,
                  const double* const G[4], int64_t R, const double* norm_r2, double* rowbuf,
                  double* sc, hipStream_t s) {
-  hipLaunchKernelGGL(weighted_rows_kernel, dim3((unsigned)R), dim3(TPB), 0, s, G[0], G[1], G[2],
-                     G[3], lam, lam, R, rowbuf);
+  hipLaunchKernelGGL(fit_rows_kernel, dim3((unsigned)R), dim3(TPB), 0, s, G[0], G[1], G[2], G[3],
+                     lam, MT, FT, n, R, rowbuf);
   CPPPL_LAUNCH_CHECK("fit_rows");
-  hipLaunchKernelGGL(fit_finish_kernel, dim3(1), dim3(TPB), 0, s, MT, FT, n, lam, R, rowbuf,
-                     norm_r2, sc);
+  hipLaunchKernelGGL(fit_finish_kernel, dim3(1), dim3(TPB), 0, s, R, rowbuf, norm_r2, sc);
   CPPPL_LAUNCH_CHECK("fit_finish");
+}
+
+void copy_doubles(const double* const* src, double* const* dst, const int64_t* n, int count,
+                  hipStream_t s) {
+  if (count < 1 || count > 5) throw std::invalid_argument("copy_doubles: 1..5 copies");
+  CopyList L{};
+  int64_t mx = 0;
+  for (int q = 0; q < count; ++q) {
+    L.src[q] = src[q];
+    L.dst[q] = dst[q];
+    L.n[q] = n[q];
+    mx = std::max(mx, n[q]);
+  }
+  L.count = count;
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>(1, (mx + TPB - 1) / TPB), 1024);
+  hipLaunchKernelGGL(copy_list_kernel, dim3((unsigned)blocks), dim3(TPB), 0, s, L);
+  CPPPL_LAUNCH_CHECK("copy_list");
 }
 
 void weighted_hadamard_sum(const double* const X[4], const double* lamA, const double* lamB,

@@ -116,10 +116,15 @@ def test_als_trajectory_fp64(lib, name):
     f_o, lam_o, hist = oracle.cp_als(r, fs, 10, norm_r2=n2, t=inp.t)
     ctx = _ctx(lib, cfg, inp)
     ctx.set_factors(*fs)
-    rep = ctx.als(10, energy=True)
+    rep = ctx.als(10, energy=True, eta=True)
     assert rep["sweeps"] == 10
     np.testing.assert_allclose(rep["fit_hist"], hist["fit"], rtol=0, atol=1e-9)
     np.testing.assert_allclose(rep["eta_hist"], hist["eta"], rtol=1e-7, atol=1e-9)
+    # without eta the sweeps are the same and eta is reported as NaN
+    ctx.set_factors(*fs)
+    rep2 = ctx.als(10)
+    np.testing.assert_allclose(rep2["fit_hist"], rep["fit_hist"], rtol=0, atol=1e-12)
+    assert np.all(np.isnan(rep2["eta_hist"]))
     assert rep["loss"] == pytest.approx(hist["loss"][-1], rel=1e-8)
     assert rep["energy_cp"] == pytest.approx(hist["energy"][-1], rel=1e-8)
     fi, fj, fa, fb, lam = ctx.get_factors()
@@ -275,3 +280,21 @@ def test_windowed_stop_rule(lib):
     else:
         assert r["sweeps"] == want + 1
         np.testing.assert_allclose(r["fit_hist"], full[:want + 1], rtol=0, atol=1e-12)
+
+
+def test_eta_stop_rule(lib):
+    """stop_rule 2 (eq. N3_stopping): the sweeps stop at the first n with
+    eta_n < tol, eta taken from a full run with eta evaluation switched on."""
+    cfg = SMALL["odd"]
+    _say("eta stop rule")
+    inp = synth.make_inputs(cfg)
+    ctx = _ctx(lib, cfg, inp, "fp64")
+    fs = synth.init_factors(cfg)
+    ctx.set_factors(*fs)
+    eta = ctx.als(40, eta=True)["eta_hist"]
+    tol = float(np.quantile(eta, 0.5))
+    want = next(n for n in range(40) if eta[n] < tol)
+    ctx.set_factors(*fs)
+    r = ctx.als(40, stop_rule=2, tol=tol)
+    assert r["sweeps"] == want + 1
+    np.testing.assert_allclose(r["eta_hist"], eta[:want + 1], rtol=1e-12, atol=0)
