@@ -81,6 +81,9 @@ typedef struct {
                             evaluation noise of BF16 fits */
   int eta;               /* non-zero: evaluate eta (eq. N3_stopping) after every sweep (implied
                             by stop_rule 2); otherwise the report's eta values are NaN */
+  int near_cache;        /* non-zero: keep the last six iterates; when the call runs n > 5
+                            sweeps, the (n-5)th becomes the near-optimal cache used by
+                            CPPPL_WS_NEAR_OPTIMAL (otherwise the previous cache stays) */
 } cpppl_als_opts;
 
 /* Kernel classes timed when opts.timing is set (index into ms_class / n_class). */
@@ -214,7 +217,9 @@ CPPPL_API cpppl_status cpppl_mlp_load(cpppl_mlp* mlp, const char* path);
 enum {
   CPPPL_WS_PLAIN = 0,       /* previous converged factors (the paper's "optimal guess") */
   CPPPL_WS_LEARNED = 1,     /* previous factors + network correction, judged against PLAIN */
-  CPPPL_WS_FIRST_ORDER = 2  /* previous factors + first-order ALS change from dR (no network) */
+  CPPPL_WS_FIRST_ORDER = 2, /* previous factors + first-order ALS change from dR (no network) */
+  CPPPL_WS_NEAR_OPTIMAL = 3 /* the near-optimal cache (see cpppl_als_opts.near_cache); PLAIN
+                               while no cache exists.  No features are formed. */
 };
 
 /* Feature width of the warm-start network for these dims: 2 (2o + 2v). */

@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "cpppl.h")
 
 FP64, BF16 = 0, 1
 PRECISIONS = {"fp64": FP64, "bf16": BF16}
-WS_PLAIN, WS_LEARNED, WS_FIRST_ORDER = 0, 1, 2
+WS_PLAIN, WS_LEARNED, WS_FIRST_ORDER, WS_NEAR_OPTIMAL = 0, 1, 2, 3
 T_CLASSES = ["kr_t2", "y", "z", "m", "g", "h", "solve", "fit", "inv"]
 
 STATUS = {0: "ok", -1: "E_ARG", -2: "E_STATE", -3: "E_HIP", -4: "E_NOMEM", -5: "E_NOT_SPD",
@@ -40,7 +40,7 @@ class AlsOpts(C.Structure):
     _fields_ = [("max_sweeps", C.c_int), ("stop_rule", C.c_int), ("tol", C.c_double),
                 ("refine_fp64_sweeps", C.c_int), ("history_cap", C.c_int), ("energy", C.c_int),
                 ("timing", C.c_int), ("refine_tol", C.c_double), ("stop_window", C.c_int),
-                ("eta", C.c_int)]
+                ("eta", C.c_int), ("near_cache", C.c_int)]
 
 
 class AlsReport(C.Structure):
@@ -249,10 +249,10 @@ class Context:
 
     # ------------------------------------------------------------------ work
     def als(self, sweeps, stop_rule=0, tol=0.0, refine=0, energy=False, timing=False,
-            refine_tol=0.0, stop_window=1, eta=False):
+            refine_tol=0.0, stop_window=1, eta=False, near_cache=False):
         cap = sweeps + refine
         opts = AlsOpts(sweeps, stop_rule, tol, refine, cap, int(bool(energy)), int(bool(timing)),
-                       refine_tol, stop_window, int(bool(eta)))
+                       refine_tol, stop_window, int(bool(eta)), int(bool(near_cache)))
         fit = np.full(cap, np.nan)
         eta_h = np.full(cap, np.nan)
         ms = np.full(cap, np.nan)

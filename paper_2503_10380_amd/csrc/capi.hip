@@ -80,6 +80,10 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   p.invA = add((size_t)R * R * 8);
   p.invB = add((size_t)R * R * 8);
   p.invD = add((size_t)INV_DBUF * 8);
+  // near-optimal cache: one factor set = (2o + 2v) R + R doubles; a ring of six plus the cache
+  const size_t set_e = (size_t)((2 * o + 2 * v) * R + R);
+  p.nearRing = add(6 * set_e * 8);
+  p.nearCache = add(set_e * 8);
   const int64_t nmax = std::max(o, v);
   p.MT = add((size_t)nmax * R * 8);
   p.stage = add((size_t)std::max<int64_t>(nmax * R, R * R) * 8);
@@ -457,6 +461,29 @@ void compute_eta(cpppl_ctx* c) {
   CPPPL_HIP(hipMemcpyAsync(sc + S_CP2_PREV, sc + S_FIT + 1, 8, hipMemcpyDeviceToDevice, c->stream));
 }
 
+// The factors (FT[0..3], lambda) as one contiguous set at `base`.
+void copy_factor_set(cpppl_ctx* c, size_t base, bool to_set) {
+  const Plan& p = c->plan;
+  const int64_t R = c->d.rank;
+  const double* src[5];
+  double* dst[5];
+  int64_t n[5];
+  size_t off = base;
+  for (int m = 0; m < 5; ++m) {
+    const int64_t e = m < 4 ? nmode(c->d, m) * R : R;
+    double* live = c->at<double>(m < 4 ? p.FT[m] : p.lam);
+    double* set = c->at<double>(off);
+    src[m] = to_set ? live : set;
+    dst[m] = to_set ? set : live;
+    n[m] = e;
+    off += (size_t)e * 8;
+  }
+  copy_doubles(src, dst, n, 5, c->stream);
+}
+size_t factor_set_bytes(const cpppl_ctx* c) {
+  return (size_t)((2 * c->d.o + 2 * c->d.v) * c->d.rank + c->d.rank) * 8;
+}
+
 void snapshot(cpppl_ctx* c) {
   const Plan& p = c->plan;
   const int64_t R = c->d.rank;
@@ -749,6 +776,12 @@ void ws_derive_t(cpppl_ctx* c) {
 }
 void ws_ensure_norm(cpppl_ctx* c) { ensure_norm(c); }
 void ws_copy(cpppl_ctx* c, size_t dst, size_t src, size_t bytes) { copy_d2d(c, dst, src, bytes); }
+bool ws_install_near_cache(cpppl_ctx* c) {
+  if (!c->near_valid) return false;
+  copy_factor_set(c, c->plan.nearCache, false);
+  init_after_factors(c);
+  return true;
+}
 void ws_sync(cpppl_ctx* c) { sync(c); }
 int64_t ws_nmode(const cpppl_dims& d, int m) { return nmode(d, m); }
 
@@ -1103,6 +1136,8 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
     if (rep->fit_hist && rep->sweeps_done < opts->history_cap) rep->fit_hist[rep->sweeps_done] = fit;
     if (rep->eta_hist && rep->sweeps_done < opts->history_cap) rep->eta_hist[rep->sweeps_done] = eta;
     if (rep->ms_hist && rep->sweeps_done < opts->history_cap) rep->ms_hist[rep->sweeps_done] = ms;
+    if (opts->near_cache)
+      copy_factor_set(c, p.nearRing + (size_t)(rep->sweeps_done % 6) * factor_set_bytes(c), true);
     rep->sweeps_done++;
     if (refining) rep->refine_done++;
     rep->fit = fit;
@@ -1122,6 +1157,11 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
       break;
     }
     prev_fit = fit;
+  }
+  if (opts->near_cache && rep->sweeps_done > 5) {  // the (n-5)th iterate becomes the cache
+    const size_t sb = factor_set_bytes(c);
+    copy_d2d(c, p.nearCache, p.nearRing + (size_t)((rep->sweeps_done - 6) % 6) * sb, sb);
+    c->near_valid = true;
   }
   if (opts->energy) {
     compute_energy(c, c->at<double>(p.scal) + S_ENERGY);

@@ -19,7 +19,7 @@ struct Plan {
   size_t t16, t16T, b16T, b16P;
   // factors (transposed, R x n), weights, snapshots, Grams
   size_t FT[4], FTprev[4], F16T[4], lam, lamprev;
-  size_t gram[4], cross[4], invA, invB, invD, MT, stage;
+  size_t gram[4], cross[4], invA, invB, invD, MT, stage, nearRing, nearCache;
   // intermediates: one region [tau | Ya | Yb | Z]; G aliases Z
   size_t big, tau, Ya, Yb, Z;
   size_t big_bytes;
@@ -74,6 +74,7 @@ struct cpppl_ctx {
   bool norm_valid = false;
   bool ybeta_valid = false;
   bool want_eta = true;  // sweeps evaluate eta (eq. N3_stopping)
+  bool near_valid = false;  // the near-optimal cache holds an iterate
   cpppl::DType ybeta_dt = cpppl::DType::F64;
   bool ws_valid = false;      // warm-start snapshot (wsF) holds the factors before the last warm start
 

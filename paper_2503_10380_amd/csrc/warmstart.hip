@@ -144,7 +144,7 @@ CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* c, const double* dt, int on_d
                                         int strategy, cpppl_mlp* mlp, int* chosen) {
   WS_TRY(c)
   if (!dt) throw std::invalid_argument("dt is NULL");
-  if (strategy < CPPPL_WS_PLAIN || strategy > CPPPL_WS_FIRST_ORDER)
+  if (strategy < CPPPL_WS_PLAIN || strategy > CPPPL_WS_NEAR_OPTIMAL)
     throw std::invalid_argument("unknown warm-start strategy");
   if (!c->ws) throw StatusError(CPPPL_E_STATE, "no workspace bound");
   if (c->planted || !c->have_t || !c->have_b || !c->have_factors)
@@ -158,6 +158,17 @@ CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* c, const double* dt, int on_d
   const Plan& p = c->plan;
   const int64_t R = c->d.rank;
   double* sc = c->at<double>(p.scal);
+
+  if (strategy == CPPPL_WS_NEAR_OPTIMAL) {  // the cached (n-5)th iterate, no features
+    ws_load_dt(c, dt, on_device);
+    axpy1(c->at<double>(p.dt64), c->at<double>(p.t64), c->d.o * c->d.o * c->d.v * c->d.v, c->stream);
+    ws_derive_t(c);
+    const bool used = ws_install_near_cache(c);
+    c->ws_valid = false;
+    ws_sync(c);
+    if (chosen) *chosen = used ? CPPPL_WS_NEAR_OPTIMAL : CPPPL_WS_PLAIN;
+    return CPPPL_OK;
+  }
 
   // previous (converged) factors
   for (int m = 0; m < 4; ++m) ws_copy(c, p.wsF[m], p.FT[m], (size_t)(ws_nmode(c->d, m) * R) * 8);

@@ -22,6 +22,7 @@ void ws_init_after_factors(cpppl_ctx* c);
 // Re-derive the operand layouts of t from the FP64 master.
 void ws_derive_t(cpppl_ctx* c);
 void ws_ensure_norm(cpppl_ctx* c);
+bool ws_install_near_cache(cpppl_ctx* c);
 void ws_copy(cpppl_ctx* c, size_t dst, size_t src, size_t bytes);
 void ws_sync(cpppl_ctx* c);
 int64_t ws_nmode(const cpppl_dims& d, int m);

@@ -174,3 +174,30 @@ def test_learned_warm_start_sequence(lib):
                       (3, "first-sweep fit gap")):
         mean = {n: float(np.mean([r[n][idx] for r in report])) for n in report[0]}
         _say(f"  mean {what}: {mean}")
+
+
+def test_near_optimal_cache(lib):
+    """The near-optimal guess: an ALS call of n > 5 sweeps caches its (n-5)th
+    iterate; a call of n <= 5 sweeps keeps the old cache; the warm start
+    NEAR_OPTIMAL installs the cache (PLAIN while none exists)."""
+    cfg = CFG
+    _say("near-optimal cache")
+    inp = synth.make_inputs(cfg)
+    fs = synth.init_factors(cfg)
+    zero = np.zeros_like(inp.t)
+    ctx = _ctx(lib, cfg, inp.t, inp.b_vv)
+    ctx.set_factors(*fs)
+    assert ctx.warm_start(zero, lib.WS_NEAR_OPTIMAL) == lib.WS_PLAIN
+    for a, b in zip(ctx.get_factors()[:4], fs):
+        np.testing.assert_array_equal(a, b)
+    ctx.als(3)
+    f3 = ctx.get_factors()
+    ctx.set_factors(*fs)
+    ctx.als(8, near_cache=True)
+    assert ctx.warm_start(zero, lib.WS_NEAR_OPTIMAL) == lib.WS_NEAR_OPTIMAL
+    for a, b in zip(ctx.get_factors(), f3):
+        np.testing.assert_array_equal(a, b)
+    ctx.als(4, near_cache=True)  # too short: the cache stays the 3rd iterate
+    assert ctx.warm_start(zero, lib.WS_NEAR_OPTIMAL) == lib.WS_NEAR_OPTIMAL
+    for a, b in zip(ctx.get_factors(), f3):
+        np.testing.assert_array_equal(a, b)
