@@ -51,10 +51,16 @@ typedef enum {
 } cpppl_status;
 
 /* Operand precision of the MTTKRP contractions.  Grams, W, the Cholesky solve,
- * the factor masters, the fit and the energy are FP64 in both. */
+ * the factor masters, the fit and the energy are FP64 in all of them, and the
+ * FP64 masters of t and B are kept for the FP64 refinement sweeps. */
 typedef enum {
-  CPPPL_FP64 = 0, /* FP64 operands, FP64 accumulation */
-  CPPPL_BF16 = 1  /* bfloat16 operands (t, B, factors, intermediates), FP32 accumulation */
+  CPPPL_FP64 = 0,    /* FP64 operands, FP64 accumulation */
+  CPPPL_BF16 = 1,    /* bfloat16 operands (t, B, factors, intermediates), FP32 accumulation */
+  CPPPL_FP8_E4M3 = 2 /* ablation: t and B stored as OCP e4m3 (largest value 448, round to
+                        nearest even) times a power-of-two scale per (ij) row of t and per
+                        X slice of B, the least one that keeps the row or slice in range;
+                        dequantised exactly to bfloat16 inside the GEMMs; factors and
+                        intermediates bfloat16, FP32 accumulation.  Needs v % 8 == 0. */
 } cpppl_precision;
 
 typedef struct {
@@ -122,7 +128,8 @@ typedef struct {
 
 /* Create a context for `dims` and operand precision `prec` on HIP device
  * `device`, enqueuing on `hip_stream` (a hipStream_t; NULL = default stream).
- * The context needs a device workspace before any other call (bind_workspace). */
+ * The context needs a device workspace before any other call (bind_workspace).
+ * E_ARG for bad dims, an unknown precision, or FP8 with v % 8 != 0. */
 CPPPL_API cpppl_status cpppl_create(const cpppl_dims* dims, cpppl_precision prec, int device,
                                     void* hip_stream, cpppl_ctx** out);
 /* Bytes of device workspace a context with these dims and precision needs. */
@@ -166,7 +173,8 @@ CPPPL_API cpppl_status cpppl_get_factors(cpppl_ctx* ctx, double* fi, double* fj,
 CPPPL_API cpppl_status cpppl_als(cpppl_ctx* ctx, const cpppl_als_opts* opts,
                                  cpppl_als_report* report);
 /* The MTTKRP of one mode (0 i, 1 j, 2 a, 3 b) at the current factors, in
- * precision `prec` (BF16 needs a BF16 context): m_out is n_mode x R (the
+ * precision `prec` (FP64, or the context's own precision; anything else is
+ * E_UNSUPPORTED): m_out is n_mode x R (the
  * numerator of eq. full_der for that factor, without lambda). */
 CPPPL_API cpppl_status cpppl_mttkrp(cpppl_ctx* ctx, int mode, cpppl_precision prec, double* m_out,
                                     int on_device);

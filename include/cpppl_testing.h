@@ -26,6 +26,28 @@ CPPPL_API cpppl_status cpppl_test_gemm(int in_dtype, int64_t M, int64_t N, int64
                                        void* C, int64_t scm, int64_t scb, int c_dtype, double alpha,
                                        double beta, int splits, void* partial, void* stream);
 
+/* As cpppl_test_gemm with BF16 A and an e4m3 B that is k-contiguous
+ * (sbk == 1, one byte per element), dequantised exactly inside the kernel and
+ * multiplied by bscale[n] (bscale_mode 1), bscale[k] (mode 2; equal within
+ * each aligned group of 8 k) or 1 (mode 0); the scales should be powers of two. */
+CPPPL_API cpppl_status cpppl_test_gemm_e4m3b(int64_t M, int64_t N, int64_t K, int64_t batch,
+                                             const void* A, int64_t sam, int64_t sak, int64_t sab,
+                                             const uint8_t* B, int64_t sbn, int64_t sbb,
+                                             const float* bscale, int bscale_mode, void* C,
+                                             int64_t scm, int64_t scb, int c_dtype, int splits,
+                                             void* partial, void* stream);
+
+/* OCP e4m3 codes of a rows x len FP64 matrix with one power-of-two scale per
+ * row (scale[r], the least 2^e with max |x[r][:]| <= 448 * 2^e), as the FP8
+ * contexts store t and B: q[r][k] = e4m3(x[r][k] / scale[r]). */
+CPPPL_API cpppl_status cpppl_test_quantize_e4m3(const double* x, int64_t rows, int64_t len,
+                                                uint8_t* q, float* scale, void* stream);
+
+/* out[i] = bfloat16 bits of decode(q[i]) * scale, by the conversion the GEMM
+ * loader uses; n a multiple of 8. */
+CPPPL_API cpppl_status cpppl_test_dequant_e4m3(const uint8_t* q, int64_t n, float scale,
+                                               uint16_t* out, void* stream);
+
 /* Y (R x n) = W^{-1} X for SPD W (R x R, overwritten; `work` holds
  * R*R + 8192 doubles) by the block sweep-operator inverse; status: 0 ok,
  * 1 bad pivot. */

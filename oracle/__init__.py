@@ -39,3 +39,4 @@ from .als import (  # noqa: F401
     eta,
 )
 from . import mlp  # noqa: F401
+from . import fp8  # noqa: F401

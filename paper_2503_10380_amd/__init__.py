@@ -17,8 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcpppl.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "cpppl.h")
 
-FP64, BF16 = 0, 1
-PRECISIONS = {"fp64": FP64, "bf16": BF16}
+FP64, BF16, FP8 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "bf16": BF16, "fp8": FP8}
 WS_PLAIN, WS_LEARNED, WS_FIRST_ORDER, WS_NEAR_OPTIMAL = 0, 1, 2, 3
 T_CLASSES = ["kr_t2", "y", "z", "m", "g", "h", "solve", "fit", "inv"]
 

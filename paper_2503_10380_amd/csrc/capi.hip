@@ -51,16 +51,25 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   };
   const int64_t o = d.o, v = d.v, X = d.nx, R = d.rank;
   const size_t o2v2 = (size_t)(o * o * v * v), xv2 = (size_t)(X * v * v);
-  const bool lp = prec == CPPPL_BF16;
+  const bool lp = prec != CPPPL_FP64;   // bfloat16 factors and intermediates
+  const bool bf = prec == CPPPL_BF16;   // bfloat16 t and B
+  const bool f8 = prec == CPPPL_FP8_E4M3;  // e4m3 t and B with scales
   p.t64 = add(o2v2 * 8);
   p.t64T = add(o2v2 * 8);
   p.b64 = add(xv2 * 8);
   p.b64T = add(xv2 * 8);
   p.b64P = add(xv2 * 8);
-  p.t16 = lp ? add(o2v2 * 2) : 0;
-  p.t16T = lp ? add(o2v2 * 2) : 0;
-  p.b16T = lp ? add(xv2 * 2) : 0;
-  p.b16P = lp ? add(xv2 * 2) : 0;
+  p.t16 = bf ? add(o2v2 * 2) : 0;
+  p.t16T = bf ? add(o2v2 * 2) : 0;
+  p.b16T = bf ? add(xv2 * 2) : 0;
+  p.b16P = bf ? add(xv2 * 2) : 0;
+  p.t8 = f8 ? add(o2v2) : 0;
+  p.t8T = f8 ? add(o2v2) : 0;
+  p.b8T = f8 ? add(xv2) : 0;
+  p.b8P = f8 ? add(xv2) : 0;
+  p.sT = f8 ? add((size_t)(o * o) * 4) : 0;
+  p.sB = f8 ? add((size_t)X * 4) : 0;
+  p.sBx = f8 ? add((size_t)(X * v) * 4) : 0;
   for (int m = 0; m < 4; ++m) {
     const size_t n = (size_t)nmode(d, m);
     p.FT[m] = add(n * R * 8);
@@ -91,8 +100,8 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   p.wsOut = add((size_t)R * (2 * o + 2 * v) * 4);
   p.dt64 = add(o2v2 * 8);
   p.dt64T = add(o2v2 * 8);
-  p.dt16 = lp ? add(o2v2 * 2) : 0;
-  p.dt16T = lp ? add(o2v2 * 2) : 0;
+  p.dt16 = bf ? add(o2v2 * 2) : 0;
+  p.dt16T = bf ? add(o2v2 * 2) : 0;
   // intermediates, sized for FP64 and shared by the BF16 path
   const size_t tau_e = (size_t)(R * v * v), y_e = (size_t)(R * X * v);
   const size_t z_e = (size_t)(R * std::max(X, v) * v);  // Z, and G (R v^2) aliased on it
@@ -172,14 +181,26 @@ Path path_for(cpppl_ctx* c, DType dt) {
     P.BnT = c->at(p.b64T);
     P.Bp = c->at(p.b64P);
     for (int m = 0; m < 4; ++m) P.FTop[m] = c->at(p.FT[m]);
-  } else {
-    if (c->prec != CPPPL_BF16) throw StatusError(CPPPL_E_UNSUPPORTED, "BF16 path needs a BF16 context");
+  } else if (c->prec == CPPPL_BF16) {
     P.esz = 2;
     P.T2 = c->at(p.t16);
     P.T2T = c->at(p.t16T);
     P.BnT = c->at(p.b16T);
     P.Bp = c->at(p.b16P);
     for (int m = 0; m < 4; ++m) P.FTop[m] = c->at(p.F16T[m]);
+  } else if (c->prec == CPPPL_FP8_E4M3) {
+    // e4m3 t and B (scaled per ij row and per X slice), bfloat16 everything else
+    P.esz = 2;
+    P.fp8 = true;
+    P.T2 = c->at(p.t8);
+    P.T2T = c->at(p.t8T);
+    P.BnT = c->at(p.b8T);
+    P.Bp = c->at(p.b8P);
+    P.sT = c->at<float>(p.sT);
+    P.sBx = c->at<float>(p.sBx);
+    for (int m = 0; m < 4; ++m) P.FTop[m] = c->at(p.F16T[m]);
+  } else {
+    throw StatusError(CPPPL_E_UNSUPPORTED, "the low-precision path needs a BF16 or FP8 context");
   }
   return P;
 }
@@ -203,12 +224,13 @@ int splits_for(cpppl_ctx* c, const Path& P, int64_t M, int64_t N, int64_t K, int
 void compute_tau(cpppl_ctx* c, const Path& P) {
   Span sp(c, CPPPL_T_KR_T2);
   const int64_t o = c->d.o, v = c->d.v, R = c->d.rank;
+  // e4m3 t: its per-ij scale runs along k here and is folded into Kt
   khatri_rao_t(c->at<double>(c->plan.FT[0]), c->at<double>(c->plan.FT[1]), o, R, c->at(c->plan.Kt),
-               P.dt, c->stream);
+               P.dt, c->stream, P.fp8 ? P.sT : nullptr);
   Gemm g;
   g.M = R; g.N = v * v; g.K = o * o;
   g.A = c->at(c->plan.Kt); g.sam = o * o; g.sak = 1;
-  g.B = P.T2T; g.sbn = o * o; g.sbk = 1;
+  g.B = P.T2T; g.sbn = o * o; g.sbk = 1; g.b_fp8 = P.fp8;
   g.C = c->at(c->plan.tau); g.scm = v * v; g.ctype = P.dt;
   run_gemm(P, g, c->stream);
 }
@@ -221,6 +243,7 @@ void compute_Y(cpppl_ctx* c, const Path& P, int mode, size_t out) {
   g.M = R; g.N = X * v; g.K = v;
   g.A = P.FTop[mode]; g.sam = v; g.sak = 1;
   g.B = P.BnT; g.sbn = v; g.sbk = 1;
+  g.b_fp8 = P.fp8; g.bscale = P.sBx; g.bscale_mode = 1;  // n = (X, q)
   g.C = c->at(out); g.scm = X * v; g.ctype = P.dt;
   run_gemm(P, g, c->stream);
 }
@@ -246,6 +269,7 @@ void compute_M(cpppl_ctx* c, const Path& P) {
   g.M = R; g.N = v; g.K = X * v;
   g.A = c->at(c->plan.Z); g.sam = X * v; g.sak = 1;
   g.B = P.Bp; g.sbn = X * v; g.sbk = 1;
+  g.b_fp8 = P.fp8; g.bscale = P.sBx; g.bscale_mode = 2;  // k = (X, q), v % 8 == 0
   g.C = c->at(c->plan.MT); g.scm = v; g.ctype = DType::F64;
   g.splits = splits_for(c, P, g.M, g.N, g.K, 1);
   g.partial = c->at(c->plan.partial);
@@ -272,6 +296,7 @@ void compute_H(cpppl_ctx* c, const Path& P) {
   g.M = R; g.N = o * o; g.K = v * v;
   g.A = c->at(c->plan.Z); g.sam = v * v; g.sak = 1;
   g.B = P.T2; g.sbn = v * v; g.sbk = 1;
+  g.b_fp8 = P.fp8; g.bscale = P.sT; g.bscale_mode = 1;  // n = ij
   g.C = c->at(c->plan.HT); g.scm = o * o; g.ctype = DType::F64;
   g.splits = splits_for(c, P, g.M, g.N, g.K, 1);
   g.partial = c->at(c->plan.partial);
@@ -328,7 +353,7 @@ void compute_gram(cpppl_ctx* c, int m) {
 }
 
 void refresh_lowp(cpppl_ctx* c, int m) {
-  if (c->prec != CPPPL_BF16) return;
+  if (c->prec == CPPPL_FP64) return;
   const int64_t n = nmode(c->d, m), R = c->d.rank;
   convert(c->at<double>(c->plan.FT[m]), c->at(c->plan.F16T[m]), DType::BF16, n * R, c->stream);
 }
@@ -703,6 +728,11 @@ void derive_t(cpppl_ctx* c) {
   if (c->prec == CPPPL_BF16) {
     convert(c->at<double>(p.t64), c->at(p.t16), DType::BF16, o2 * v2, c->stream);
     transpose_batched(c->at<double>(p.t64), c->at(p.t16T), DType::BF16, 1, o2, v2, c->stream);
+  } else if (c->prec == CPPPL_FP8_E4M3) {
+    float* sT = c->at<float>(p.sT);
+    e4m3_row_scales(c->at<double>(p.t64), o2, v2, sT, c->stream);
+    quantize_e4m3(c->at<double>(p.t64), c->at<uint8_t>(p.t8), o2 * v2, sT, v2, o2, 1, c->stream);
+    quantize_e4m3(c->at<double>(p.t64T), c->at<uint8_t>(p.t8T), o2 * v2, sT, 1, o2, 1, c->stream);
   }
 }
 
@@ -734,6 +764,7 @@ void ws_solve_no_update(cpppl_ctx* c, int mode, size_t out_off) {
 void ws_init_after_factors(cpppl_ctx* c) { init_after_factors(c); }
 void ws_mttkrp_dt(cpppl_ctx* c, int mode) {
   // the MTTKRP chain with dt in place of t (the PPL tensor is linear in t)
+  // BF16 contexts use a bfloat16 copy of dt; FP64 and FP8 contexts the FP64 one
   const DType dt = c->prec == CPPPL_BF16 ? DType::BF16 : DType::F64;
   Path P = path_for(c, dt);
   if (dt == DType::F64) {
@@ -830,7 +861,8 @@ CPPPL_API cpppl_status cpppl_workspace_size(const cpppl_dims* dims, cpppl_precis
   if (!bytes) return CPPPL_E_ARG;
   try {
     validate_dims(dims);
-    if (prec != CPPPL_FP64 && prec != CPPPL_BF16) return CPPPL_E_ARG;
+    if (prec != CPPPL_FP64 && prec != CPPPL_BF16 && prec != CPPPL_FP8_E4M3) return CPPPL_E_ARG;
+    if (prec == CPPPL_FP8_E4M3 && dims->v % 8 != 0) return CPPPL_E_ARG;
     *bytes = build_plan(*dims, prec).total;
   } catch (...) {
     return CPPPL_E_ARG;
@@ -847,7 +879,8 @@ CPPPL_API cpppl_status cpppl_create(const cpppl_dims* dims, cpppl_precision prec
   } catch (...) {
     return CPPPL_E_ARG;
   }
-  if (prec != CPPPL_FP64 && prec != CPPPL_BF16) return CPPPL_E_ARG;
+  if (prec != CPPPL_FP64 && prec != CPPPL_BF16 && prec != CPPPL_FP8_E4M3) return CPPPL_E_ARG;
+  if (prec == CPPPL_FP8_E4M3 && dims->v % 8 != 0) return CPPPL_E_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CPPPL_E_HIP;
   cpppl_ctx* c = new (std::nothrow) cpppl_ctx();
@@ -935,6 +968,12 @@ CPPPL_API cpppl_status cpppl_load_df(cpppl_ctx* c, const double* b, int on_devic
   if (c->prec == CPPPL_BF16) {
     transpose_batched(c->at<double>(p.b64), c->at(p.b16T), DType::BF16, X, v, v, c->stream);
     permute_pxq(c->at<double>(p.b64), c->at(p.b16P), DType::BF16, X, v, c->stream);
+  } else if (c->prec == CPPPL_FP8_E4M3) {
+    float* sB = c->at<float>(p.sB);
+    e4m3_row_scales(c->at<double>(p.b64), X, v * v, sB, c->stream);
+    quantize_e4m3(c->at<double>(p.b64T), c->at<uint8_t>(p.b8T), n, sB, v * v, X, 1, c->stream);
+    quantize_e4m3(c->at<double>(p.b64P), c->at<uint8_t>(p.b8P), n, sB, 1, X * v, v, c->stream);
+    expand_scales(sB, c->at<float>(p.sBx), X, v, c->stream);
   }
   c->have_b = true;
   c->planted = false;
@@ -1038,8 +1077,9 @@ CPPPL_API cpppl_status cpppl_mttkrp(cpppl_ctx* c, int mode, cpppl_precision prec
   if (mode < 0 || mode > 3) throw std::invalid_argument("mode must be 0..3");
   if (!m_out) throw std::invalid_argument("m_out is NULL");
   require_inputs(c);
-  const DType dt = prec == CPPPL_BF16 ? DType::BF16 : DType::F64;
-  mttkrp_into_MT(c, path_for(c, dt), mode);
+  if (prec != CPPPL_FP64 && prec != c->prec)
+    throw StatusError(CPPPL_E_UNSUPPORTED, "MTTKRP precision must be FP64 or the context's");
+  mttkrp_into_MT(c, path_for(c, prec == CPPPL_FP64 ? DType::F64 : DType::BF16), mode);
   const int64_t n = nmode(c->d, mode), R = c->d.rank;
   transpose_batched(c->at<double>(c->plan.MT), c->at(c->plan.stage), DType::F64, 1, R, n, c->stream);
   CPPPL_HIP(hipMemcpyAsync(m_out, c->at(c->plan.stage), (size_t)(n * R) * 8,
@@ -1100,8 +1140,8 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
   rep->ridge_retries = 0;
   rep->energy_cp = std::numeric_limits<double>::quiet_NaN();
   for (int k = 0; k < 16; ++k) { rep->ms_class[k] = 0.0; rep->n_class[k] = 0; }
-  const DType main_dt = c->prec == CPPPL_BF16 ? DType::BF16 : DType::F64;
-  const int total = opts->max_sweeps + (c->prec == CPPPL_BF16 ? opts->refine_fp64_sweeps : 0);
+  const DType main_dt = c->prec != CPPPL_FP64 ? DType::BF16 : DType::F64;
+  const int total = opts->max_sweeps + (c->prec != CPPPL_FP64 ? opts->refine_fp64_sweeps : 0);
   double prev_fit = std::numeric_limits<double>::quiet_NaN();
   auto t_start = std::chrono::steady_clock::now();
   sync(c);

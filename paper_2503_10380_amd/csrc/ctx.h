@@ -17,6 +17,9 @@ struct Plan {
   size_t t64, t64T, tdc, b64, b64T, b64P;
   // bfloat16 operand copies (BF16 contexts)
   size_t t16, t16T, b16T, b16P;
+  // e4m3 operand copies and their power-of-two scales (FP8 contexts): sT per ij,
+  // sB per X, sBx[X*v + q] = sB[X]
+  size_t t8, t8T, b8T, b8P, sT, sB, sBx;
   // factors (transposed, R x n), weights, snapshots, Grams
   size_t FT[4], FTprev[4], F16T[4], lam, lamprev;
   size_t gram[4], cross[4], invA, invB, invD, MT, stage, nearRing, nearCache;
@@ -48,6 +51,9 @@ enum Scal {  // slots of the device scalar block
 struct Path {
   DType dt;
   size_t esz;
+  bool fp8 = false;          // T2, T2T, BnT, Bp hold e4m3 codes
+  const float* sT = nullptr;   // scale of t row ij
+  const float* sBx = nullptr;  // scale of B^X, repeated per (X, q)
   const void* T2;   // t[ij][cd]   (o^2 x v^2)
   const void* T2T;  // t[cd][ij]   (v^2 x o^2)
   const void* BnT;  // B[X][q][p]  = B^X_pq

@@ -28,11 +28,19 @@ struct Gemm {
   double alpha = 1.0, beta = 0.0;
   int splits = 1;
   void* partial = nullptr;
+  // gemm_bf16 only: B holds OCP e4m3 codes (one byte each, k-contiguous),
+  // dequantised to bfloat16 on the way into LDS and multiplied by a scale
+  // (exact for power-of-two scales): bscale_mode 0 none, 1 bscale[n] (per
+  // column of C), 2 bscale[k] (must be equal within each aligned group of 8 k).
+  bool b_fp8 = false;
+  const float* bscale = nullptr;
+  int bscale_mode = 0;
 };
 
 // A and B in FP64, accumulation in FP64 (v_mfma_f64_16x16x4f64).
 void gemm_f64(const Gemm& g, hipStream_t s);
-// A and B in bfloat16, accumulation in FP32 (v_mfma_f32_16x16x32_bf16); beta must be 0.
+// A and B in bfloat16 (B optionally e4m3, see Gemm::b_fp8), accumulation in
+// FP32 (v_mfma_f32_16x16x32_bf16); beta must be 0 unless split.
 void gemm_bf16(const Gemm& g, hipStream_t s);
 
 // Split count giving roughly `target_blocks` work-groups, with at least

@@ -21,6 +21,8 @@
 // so the larger operand is streamed from HBM about once.
 #include "gemm.h"
 
+#include "fp8.h"
+
 #include <algorithm>
 #include <type_traits>
 #include <stdexcept>
@@ -42,8 +44,10 @@ struct KArgs {
   int64_t kchunk;
   void* partial;
   int64_t tiles_m, tiles_n;
-  int vec_ok;    // 16-byte operand loads allowed
+  int vec_ok;    // 16-byte operand loads allowed (8-byte for e4m3 B)
   int cvec_ok;   // 16-byte result stores allowed
+  const float* bscale;  // e4m3 B: scale per column (mode 1) or per k (mode 2)
+  int bscale_mode;
 };
 
 struct Coords {
@@ -283,15 +287,69 @@ struct BfTile {
   }
 };
 
+// A k-contiguous B tile stored as e4m3 codes: each lane keeps its chunks of 8
+// codes (8 bytes) and their scale in registers while the matrix cores work on
+// the previous slice, then writes them to LDS as bfloat16 in the layout of
+// BfTile<ROWS, true, BBK>, so the fragment reads are those of the BF16 kernel.
+template <int ROWS, int BBK>
+struct F8Tile {
+  using L = BfTile<ROWS, true, BBK>;
+  static constexpr int C = L::C;
+  struct Regs {
+    uint2 q[C];
+    float s[C];
+  };
+  // scales that do not change along k (mode 0: 1, mode 1: per row)
+  __device__ __forceinline__ static void init_scales(Regs& r, const KArgs& a, int64_t row0,
+                                                     int64_t nrows, int tid) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const int64_t g = row0 + (tid + e * 256) / (BBK / 8);
+      r.s[e] = (a.bscale_mode == 1 && g < nrows) ? a.bscale[g] : 1.0f;
+    }
+  }
+  __device__ __forceinline__ static void load(Regs& r, const uint8_t* X, int64_t s_row, int64_t row0,
+                                              int64_t nrows, int64_t k0, int64_t kend, bool vec,
+                                              const KArgs& a, int tid) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const int c = tid + e * 256;
+      const int row = c / (BBK / 8), kk = (c % (BBK / 8)) * 8;
+      const int64_t g = row0 + row, gk = k0 + kk;
+      const uint8_t* p = X + g * s_row + gk;
+      if (vec && g < nrows && gk + 8 <= kend) {
+        r.q[e] = *(const uint2*)p;
+      } else {
+        const int64_t cnt = g < nrows ? kend - gk : 0;
+        uint32_t w[2] = {0u, 0u};
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < cnt) w[q >> 2] |= (uint32_t)p[q] << (8 * (q & 3));
+        r.q[e] = make_uint2(w[0], w[1]);
+      }
+      if (a.bscale_mode == 2) r.s[e] = gk < kend ? a.bscale[gk] : 1.0f;
+    }
+  }
+  __device__ __forceinline__ static void store(const Regs& r, bf16_t* S, int tid) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const int c = tid + e * 256;
+      const int row = c / (BBK / 8), kk = (c % (BBK / 8)) * 8;
+      *(uint4*)&S[L::kc_off(row, kk)] = e4m3x8_to_bf16(r.q[e], r.s[e]);
+    }
+  }
+};
+
 template <typename OutT>
 __device__ __forceinline__ OutT to_out(float v);
 template <> __device__ __forceinline__ float to_out<float>(float v) { return v; }
 template <> __device__ __forceinline__ bf16_t to_out<bf16_t>(float v) { return f32_to_bf16(v); }
 template <> __device__ __forceinline__ double to_out<double>(float v) { return (double)v; }
 
-template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT>
+template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT, bool B8 = false>
 __global__ __launch_bounds__(256, BBK == BBK_LONG ? 2 : ((AK && BKC && sizeof(OutT) <= 4) ? 4 : 3))
 void gemm_bf16_kernel(const KArgs a) {
+  static_assert(!B8 || BKC, "an e4m3 B operand must be k-contiguous");
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   using TA = BfTile<BM, AK, BBK>;
@@ -321,7 +379,10 @@ void gemm_bf16_kernel(const KArgs a) {
   const int64_t sa_row = AK ? a.sam : 1, sa_k = AK ? 1 : a.sak;
   const int64_t sb_row = BKC ? a.sbn : 1, sb_k = BKC ? 1 : a.sbk;
 
-  uint4 ra[TA::C], rb[TB::C];
+  using T8 = F8Tile<BN, BBK>;
+  uint4 ra[TA::C], rb[B8 ? 1 : TB::C];
+  typename T8::Regs r8;
+  if constexpr (B8) T8::init_scales(r8, a, n0, a.N, tid);
   f4_t acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -331,9 +392,11 @@ void gemm_bf16_kernel(const KArgs a) {
   const int64_t nk = kend > kbeg ? (kend - kbeg + BBK - 1) / BBK : 0;
   if (nk > 0) {
     TA::load(ra, A, sa_row, sa_k, m0, a.M, kbeg, kend, vec, tid);
-    TB::load(rb, B, sb_row, sb_k, n0, a.N, kbeg, kend, vec, tid);
+    if constexpr (B8) T8::load(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, kbeg, kend, vec, a, tid);
+    else TB::load(rb, B, sb_row, sb_k, n0, a.N, kbeg, kend, vec, tid);
     TA::store(ra, As, tid);
-    TB::store(rb, Bs, tid);
+    if constexpr (B8) T8::store(r8, Bs, tid);
+    else TB::store(rb, Bs, tid);
   }
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
@@ -343,7 +406,8 @@ void gemm_bf16_kernel(const KArgs a) {
     if (kt + 1 < nk) {
       const int64_t k1 = kbeg + (kt + 1) * BBK;
       TA::load(ra, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
-      TB::load(rb, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
+      if constexpr (B8) T8::load(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, k1, kend, vec, a, tid);
+      else TB::load(rb, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
     }
 #pragma unroll
     for (int ks = 0; ks < BBK; ks += 32) {
@@ -360,7 +424,8 @@ void gemm_bf16_kernel(const KArgs a) {
     }
     if (kt + 1 < nk) {
       TA::store(ra, As + (cur ^ 1) * AS, tid);
-      TB::store(rb, Bs + (cur ^ 1) * BS, tid);
+      if constexpr (B8) T8::store(r8, Bs + (cur ^ 1) * BS, tid);
+      else TB::store(rb, Bs + (cur ^ 1) * BS, tid);
     }
     __syncthreads();
   }
@@ -489,6 +554,8 @@ KArgs make_args(const Gemm& g, int BM, int BN, int BK) {
   a.tiles_n = (g.N + BN - 1) / BN;
   a.vec_ok = 0;
   a.cvec_ok = 0;
+  a.bscale = g.bscale;
+  a.bscale_mode = g.b_fp8 ? g.bscale_mode : 0;
   return a;
 }
 
@@ -540,15 +607,15 @@ void gemm_f64(const Gemm& g, hipStream_t s) {
   if (a.splits > 1) launch_reduce<double, double>(a, s);
 }
 
-template <int BK, bool AK, bool BKC>
+template <int BK, bool AK, bool BKC, bool B8 = false>
 static void launch_bf16(const KArgs& a, DType ct, dim3 grid, hipStream_t s) {
   constexpr int BM = 128, BN = 128;
   if (ct == DType::F32 || a.splits > 1)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, float>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, float, B8>), grid, dim3(256), 0, s, a);
   else if (ct == DType::BF16)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, bf16_t>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, bf16_t, B8>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, double>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, double, B8>), grid, dim3(256), 0, s, a);
 }
 
 template <int BK>
@@ -569,23 +636,40 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
   KArgs a = make_args(g, BM, BN, bk_slice);
   if (a.splits > 1 && !a.partial) throw std::invalid_argument("gemm_bf16: split-K needs a partial buffer");
   const bool ak = g.sak == 1, bk = g.sbk == 1;
-  // 16-byte vector loads need 16-byte aligned rows along the contiguous index.
-  auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  if (g.b_fp8) {
+    if (!bk) throw std::invalid_argument("gemm_bf16: an e4m3 B must be k-contiguous");
+    if (g.bscale_mode < 0 || g.bscale_mode > 2) throw std::invalid_argument("gemm_bf16: bad bscale_mode");
+    if (g.bscale_mode != 0 && !g.bscale) throw std::invalid_argument("gemm_bf16: bscale is NULL");
+  }
+  // Vector loads need aligned rows along the contiguous index: 16 bytes for
+  // 8 bfloat16, 8 bytes for 8 e4m3 codes.
+  auto al = [](const void* p, uintptr_t b) { return ((uintptr_t)p & (b - 1)) == 0; };
   const int64_t sa_row = ak ? g.sam : g.sak, sb_row = bk ? g.sbn : g.sbk;
-  a.vec_ok = (al(g.A) && al(g.B) && sa_row % 8 == 0 && sb_row % 8 == 0 && g.sab % 8 == 0 &&
-              g.sbb % 8 == 0) ? 1 : 0;
+  a.vec_ok = (al(g.A, 16) && al(g.B, g.b_fp8 ? 8 : 16) && sa_row % 8 == 0 && sb_row % 8 == 0 &&
+              g.sab % 8 == 0 && g.sbb % 8 == 0) ? 1 : 0;
   if (a.splits > 1) {
-    a.cvec_ok = (al(g.partial) && g.N % 4 == 0) ? 1 : 0;
+    a.cvec_ok = (al(g.partial, 16) && g.N % 4 == 0) ? 1 : 0;
   } else {
     const int64_t epc = g.ctype == DType::BF16 ? 8 : (g.ctype == DType::F32 ? 4 : 2);
-    a.cvec_ok = (al(g.C) && g.scm % epc == 0 && g.scb % epc == 0) ? 1 : 0;
+    a.cvec_ok = (al(g.C, 16) && g.scm % epc == 0 && g.scb % epc == 0) ? 1 : 0;
   }
   const int64_t blocks = a.tiles_m * a.tiles_n * a.batch * a.splits;
   if (blocks == 0) return;
   if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_bf16: grid too large");
   dim3 grid((unsigned)blocks);
-  if (bk_slice == BBK_LONG) launch_bf16_layout<BBK_LONG>(a, ak, bk, g.ctype, grid, s);
-  else launch_bf16_layout<BBK_SHORT>(a, ak, bk, g.ctype, grid, s);
+  if (g.b_fp8) {
+    if (bk_slice == BBK_LONG) {
+      if (ak) launch_bf16<BBK_LONG, true, true, true>(a, g.ctype, grid, s);
+      else launch_bf16<BBK_LONG, false, true, true>(a, g.ctype, grid, s);
+    } else {
+      if (ak) launch_bf16<BBK_SHORT, true, true, true>(a, g.ctype, grid, s);
+      else launch_bf16<BBK_SHORT, false, true, true>(a, g.ctype, grid, s);
+    }
+  } else if (bk_slice == BBK_LONG) {
+    launch_bf16_layout<BBK_LONG>(a, ak, bk, g.ctype, grid, s);
+  } else {
+    launch_bf16_layout<BBK_SHORT>(a, ak, bk, g.ctype, grid, s);
+  }
   CPPPL_LAUNCH_CHECK("gemm_bf16");
   if (a.splits > 1) {
     if (g.ctype == DType::F32) launch_reduce<float, float>(a, s);

@@ -21,9 +21,17 @@ void permute_pxq(const double* b, void* out, DType ot, int64_t nx, int64_t v, hi
 void convert(const double* x, void* y, DType yt, int64_t n, hipStream_t s);
 // y[i] += x[i] (FP64).
 void axpy1(const double* x, double* y, int64_t n, hipStream_t s);
-// Kt[r][i*o + j] = gT[r][i] * rT[r][j], converted to `kt`.
+// Kt[r][i*o + j] = gT[r][i] * rT[r][j] (* ij_scale[i*o + j] when given), converted to `kt`.
 void khatri_rao_t(const double* gT, const double* rT, int64_t o, int64_t R, void* Kt, DType kt,
-                  hipStream_t s);
+                  hipStream_t s, const float* ij_scale = nullptr);
+// OCP e4m3 copies with power-of-two scales:
+// scale[r] = least 2^e (e in [-126, 127]) with max_k |x[r][k]| <= 448 * 2^e, rows x len row-major;
+void e4m3_row_scales(const double* x, int64_t rows, int64_t len, float* scale, hipStream_t s);
+// q[i] = e4m3(x[i] / scale[((i / div) % mod) / grp]), round to nearest even, saturating;
+void quantize_e4m3(const double* x, uint8_t* q, int64_t n, const float* scale, int64_t div,
+                   int64_t mod, int64_t grp, hipStream_t s);
+// out[X*v + q] = scale[X].
+void expand_scales(const float* scale, float* out, int64_t nx, int64_t v, hipStream_t s);
 // w = g1 .* g2 .* g3 (n elements); g3 may be null.
 void hadamard(const double* g1, const double* g2, const double* g3, double* w, int64_t n,
               hipStream_t s);

@@ -3,6 +3,8 @@
 // no floating-point atomics.
 #include "ops.h"
 
+#include "fp8.h"
+
 #include <algorithm>
 #include <stdexcept>
 
@@ -88,14 +90,60 @@ __global__ void axpy1_kernel(const double* __restrict__ x, double* y, int64_t n)
 }
 
 __global__ void kr_kernel(const double* __restrict__ gT, const double* __restrict__ rT, int64_t o,
-                          int64_t R, void* Kt, DType kt) {
+                          int64_t R, void* Kt, DType kt, const float* __restrict__ ij_scale) {
   const int64_t total = R * o * o;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / (o * o), ij = e % (o * o);
     const int64_t i = ij / o, j = ij % o;
-    put_dt(Kt, kt, e, gT[r * o + i] * rT[r * o + j]);
+    double k = gT[r * o + i] * rT[r * o + j];
+    if (ij_scale) k *= (double)ij_scale[ij];
+    put_dt(Kt, kt, e, k);
   }
+}
+
+// One work-group per row: the least power of two 2^e (e in [-126, 127]) with
+// max |x| <= 448 * 2^e, i.e. the row scaled by 2^-e fits the e4m3 range.
+__global__ __launch_bounds__(TPB) void e4m3_scale_kernel(const double* __restrict__ x, int64_t len,
+                                                         float* scale) {
+  __shared__ double sh[TPB];
+  const double* row = x + blockIdx.x * len;
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += TPB) m = fmax(m, fabs(row[i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    m = sh[0];
+    int e = 0;
+    if (m > 0.0) {
+      int k;
+      frexp(m / 448.0, &k);  // m / 448 in [2^(k-1), 2^k) up to rounding
+      e = k < -126 ? -126 : (k > 127 ? 127 : k);
+      while (e > -126 && m <= ldexp(448.0, e - 1)) --e;  // exact comparisons
+      while (e < 127 && m > ldexp(448.0, e)) ++e;
+    }
+    scale[blockIdx.x] = ldexpf(1.0f, e);
+  }
+}
+
+__global__ void quantize_e4m3_kernel(const double* __restrict__ x, uint8_t* q, int64_t n,
+                                     const float* __restrict__ scale, int64_t div, int64_t mod,
+                                     int64_t grp) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double s = (double)scale[((i / div) % mod) / grp];
+    q[i] = e4m3_encode(x[i] / s);
+  }
+}
+
+__global__ void expand_scales_kernel(const float* __restrict__ sc, float* out, int64_t nx, int64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nx * v;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = sc[i / v];
 }
 
 __global__ void hadamard_kernel(const double* __restrict__ g1, const double* __restrict__ g2,
@@ -379,9 +427,32 @@ void axpy1(const double* x, double* y, int64_t n, hipStream_t s) {
 }
 
 void khatri_rao_t(const double* gT, const double* rT, int64_t o, int64_t R, void* Kt, DType kt,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(kr_kernel, dim3(blocks_for(R * o * o)), dim3(TPB), 0, s, gT, rT, o, R, Kt, kt);
+                  hipStream_t s, const float* ij_scale) {
+  hipLaunchKernelGGL(kr_kernel, dim3(blocks_for(R * o * o)), dim3(TPB), 0, s, gT, rT, o, R, Kt, kt,
+                     ij_scale);
   CPPPL_LAUNCH_CHECK("khatri_rao");
+}
+
+void e4m3_row_scales(const double* x, int64_t rows, int64_t len, float* scale, hipStream_t s) {
+  if (rows <= 0) return;
+  if (rows > 0x7fffffffLL) throw std::invalid_argument("e4m3_row_scales: too many rows");
+  hipLaunchKernelGGL(e4m3_scale_kernel, dim3((unsigned)rows), dim3(TPB), 0, s, x, len, scale);
+  CPPPL_LAUNCH_CHECK("e4m3_row_scales");
+}
+
+void quantize_e4m3(const double* x, uint8_t* q, int64_t n, const float* scale, int64_t div,
+                   int64_t mod, int64_t grp, hipStream_t s) {
+  if (n <= 0) return;
+  if (div <= 0 || mod <= 0 || grp <= 0) throw std::invalid_argument("quantize_e4m3: bad scale map");
+  hipLaunchKernelGGL(quantize_e4m3_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, x, q, n, scale, div,
+                     mod, grp);
+  CPPPL_LAUNCH_CHECK("quantize_e4m3");
+}
+
+void expand_scales(const float* scale, float* out, int64_t nx, int64_t v, hipStream_t s) {
+  if (nx * v <= 0) return;
+  hipLaunchKernelGGL(expand_scales_kernel, dim3(blocks_for(nx * v)), dim3(TPB), 0, s, scale, out, nx, v);
+  CPPPL_LAUNCH_CHECK("expand_scales");
 }
 
 void hadamard(const double* g1, const double* g2, const double* g3, double* w, int64_t n,
