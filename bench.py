@@ -46,16 +46,19 @@ def class_flops(cfg):
     }
 
 
-def class_bytes(cfg, esz=2):
-    """Algorithmic HBM bytes per launch: operands read once, result written once."""
+def class_bytes(cfg, esz=2, in_esz=None):
+    """Algorithmic HBM bytes per launch: operands read once, result written once.
+    esz: bytes per factor / intermediate element; in_esz: per t and B element
+    (default esz; 1 for e4m3, whose per-row scales are negligible)."""
     o, v, x, r = cfg.o, cfg.v, cfg.nx, cfg.rank
+    ei = esz if in_esz is None else in_esz
     return {
-        "kr_t2": esz * (r * o * o + o * o * v * v + r * v * v),
-        "y": esz * (r * v + x * v * v + r * x * v),
+        "kr_t2": esz * (r * o * o + r * v * v) + ei * o * o * v * v,
+        "y": esz * (r * v + r * x * v) + ei * x * v * v,
         "z": esz * (r * x * v + r * v * v + r * x * v),
-        "m": esz * (r * x * v + x * v * v) + 8 * r * v,
+        "m": esz * r * x * v + ei * x * v * v + 8 * r * v,
         "g": esz * (2 * r * x * v + r * v * v),
-        "h": esz * (r * v * v + o * o * v * v) + 8 * r * o * o,
+        "h": esz * r * v * v + ei * o * o * v * v + 8 * r * o * o,
     }
 
 
@@ -246,6 +249,112 @@ def time_to_fit(cp, torch, cfg, inp, fs, dev_t, dev_b, args):
     return res
 
 
+def _common_warm_start(cp, torch, cfg, inp, fs, dev_b, args):
+    """Factors converged on the previous amplitude step (BF16 sweeps to
+    |dfit| < 1e-3, then FP64 to 1e-6) and t after one amplitude step."""
+    ctx = cp.Context(cfg.o, cfg.v, cfg.nx, cfg.rank, "bf16")
+    ctx.load_t2(torch.tensor(inp.t, device="cuda"))
+    ctx.load_df(dev_b)
+    ctx.set_factors(*fs)
+    prep = ctx.als(args.prep_sweeps, stop_rule=1, tol=1e-3, refine=args.prep_sweeps,
+                   refine_tol=1e-6)
+    state = ctx.get_factors()
+    ctx.close()
+    del ctx
+    t1 = inp.t + synth.perturbation(cfg, 0, inp.t)
+    return state, t1, prep
+
+
+def precision_ablation(cp, torch, args):
+    """FP64, BF16 and FP8 (e4m3 t and B with power-of-two scales) on one
+    workload: sweep rate and per-class kernel times; the MTTKRP error of each
+    mode against the FP64 path at the same factors; and, from a common warm
+    start after one amplitude step, low-precision sweeps until the fit change
+    (averaged over 8 sweeps) is below the precision's floor, then FP64
+    refinement until |dfit| < tol, against plain FP64 ALS to the same tol."""
+    cfg = synth.CONFIGS[args.config]
+    inp = synth.make_inputs(cfg)
+    fs = synth.init_factors(cfg)
+    dev_b = torch.tensor(inp.b_vv, device="cuda")
+    state, t1, prep = _common_warm_start(cp, torch, cfg, inp, fs, dev_b, args)
+    dev_t = torch.tensor(t1, device="cuda")
+    del inp
+    tol = args.ablation_tol
+    floors = {"bf16": args.bf16_floor, "fp8": args.fp8_floor}
+    flops = class_flops(cfg)
+    res = {"workload": cfg.name, "o": cfg.o, "v": cfg.v, "nx": cfg.nx, "rank": cfg.rank,
+           "protocol": ("rate: --steps sweeps from the warm start after --warmup; mttkrp error: "
+                        "all four modes at the warm-start factors vs the FP64 path; fit/energy: "
+                        f"low-precision sweeps until |dfit| (8-sweep mean) < floor, then FP64 "
+                        f"refinement until |dfit| < {tol:g}, vs FP64 ALS until |dfit| < {tol:g}"),
+           "prep_sweeps": prep["sweeps"], "floors": floors, "precisions": {}}
+    m64 = None
+    ref = None
+    for prec in ("fp64", "bf16", "fp8"):
+        print(f"ablation: {prec}", file=sys.stderr, flush=True)
+        ctx = cp.Context(cfg.o, cfg.v, cfg.nx, cfg.rank, prec)
+        ctx.load_t2(dev_t)
+        ctx.load_df(dev_b)
+        _, e_exact = ctx.norm_r2()
+        ctx.set_factors(*state)
+        ms = [ctx.mttkrp(m) for m in range(4)]
+        if prec == "fp64":
+            m64 = ms
+        errs = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(ms, m64)]
+        if args.warmup:
+            ctx.als(args.warmup)
+        ctx.set_factors(*state)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.als(args.steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ctx.set_factors(*state)
+        rep = ctx.als(args.steps, timing=True)
+        nbytes = class_bytes(cfg, esz=8 if prec == "fp64" else 2,
+                             in_esz={"fp64": 8, "bf16": 2, "fp8": 1}[prec])
+        per_class = {}
+        for k in CLASSES:
+            n = rep["n_class"][k]
+            kms = rep["ms_class"][k]
+            if n and kms > 0:
+                per_class[k] = {"ms_per_launch": kms / n, "tflops": flops[k] * n / (kms * 1e-3) / 1e12,
+                                "gbs": nbytes[k] * n / (kms * 1e-3) / 1e9}
+        mt_ms = sum(rep["ms_class"][k] for k in CLASSES)
+        ctx.set_factors(*state)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if prec == "fp64":
+            r = ctx.als(args.max_sweeps, stop_rule=1, tol=tol, energy=True)
+        else:
+            r = ctx.als(args.max_sweeps, stop_rule=1, tol=max(tol, floors[prec]), stop_window=8,
+                        refine=args.max_sweeps, refine_tol=tol, energy=True)
+        t_fit = time.perf_counter() - t0
+        entry = {
+            "sweeps_per_s": args.steps / wall, "ms_per_sweep": wall * 1e3 / args.steps,
+            "mttkrp_tflops": sweep_flops(cfg) * args.steps / (mt_ms * 1e-3) / 1e12,
+            "per_class": per_class,
+            "mttkrp_rel_err_vs_fp64": errs,
+            "to_tol": {"low_sweeps": r["sweeps"] - r["refine_sweeps"],
+                       "fp64_sweeps": r["refine_sweeps"] if prec != "fp64" else r["sweeps"],
+                       "wall_s": t_fit, "fit": r["fit"], "energy": r["energy_cp"],
+                       "energy_exact": e_exact, "fit_hist": [float(f) for f in r["fit_hist"]]},
+        }
+        if prec == "fp64":
+            ref = entry["to_tol"]
+        else:
+            entry["to_tol"]["fit_rel_diff"] = abs(r["fit"] - ref["fit"]) / abs(ref["fit"])
+            entry["to_tol"]["energy_abs_diff"] = abs(r["energy_cp"] - ref["energy"])
+            entry["to_tol"]["energy_rel_diff"] = abs(r["energy_cp"] - ref["energy"]) / abs(ref["energy"])
+            entry["to_tol"]["speedup_vs_fp64"] = ref["wall_s"] / t_fit
+        res["precisions"][prec] = entry
+        print(json.dumps({prec: entry}), file=sys.stderr, flush=True)
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    return res
+
+
 def warmstart_experiment(cp, torch, args):
     """Learned vs plain vs first-order warm start over a CCSD-like amplitude
     sequence (C4 by default): t^(k+1) = t^(k) + 0.3^(k mod 10) eps_k, 20 steps.
@@ -335,7 +444,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C3")
+    ap.add_argument("--config", default=None,
+                    help="workload (default C3; C4 for --experiment warmstart, C5 for precision)")
     ap.add_argument("--prep-sweeps", type=int, default=60,
                     help="cap on the BF16 and on the FP64 sweeps that converge the previous step")
     ap.add_argument("--bf16-floor", type=float, default=1e-6,
@@ -344,8 +454,13 @@ def main():
                     help="cap on the sweeps of each time-to-fit run (and on the refinement)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--experiment", choices=["warmstart"],
-                    help="run the learned warm-start experiment (C4 unless --config) instead")
+    ap.add_argument("--fp8-floor", type=float, default=1e-4,
+                    help="precision ablation: fit-change floor of the FP8 sweeps")
+    ap.add_argument("--ablation-tol", type=float, default=1e-5,
+                    help="precision ablation: |dfit| tolerance of the FP64 phase")
+    ap.add_argument("--experiment", choices=["warmstart", "precision"],
+                    help="warmstart: the learned warm-start experiment (C4 unless --config); "
+                         "precision: the FP64 / BF16 / FP8 ablation (C5 unless --config)")
     ap.add_argument("--ws-epochs", type=int, default=300)
     ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
@@ -357,9 +472,14 @@ def main():
     if args.experiment == "warmstart":
         import torch
         import paper_2503_10380_amd as cp
-        if args.config == "C3":
-            args.config = "C4"
+        args.config = args.config or "C4"
         print(json.dumps(warmstart_experiment(cp, torch, args)))
+        return
+    if args.experiment == "precision":
+        import torch
+        import paper_2503_10380_amd as cp
+        args.config = args.config or "C5"
+        print(json.dumps(precision_ablation(cp, torch, args)))
         return
     if args.digest_counters:
         digest_counters(args.digest_counters[0], args.digest_counters[1], args.steps,
@@ -384,7 +504,7 @@ def main():
         print(f"copy calibration: 3 copies of {args.copy_calibration} MiB", file=sys.stderr)
         del src, dst
 
-    cfg = synth.CONFIGS[args.config]
+    cfg = synth.CONFIGS[args.config or "C3"]
     inp = synth.make_inputs(cfg)
     fs = synth.init_factors(cfg)
     dev_t = torch.tensor(inp.t, device="cuda")
