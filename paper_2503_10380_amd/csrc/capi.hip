@@ -122,7 +122,8 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   p.rowbuf = add((size_t)std::max<int64_t>(2 * R, 4096) * 8);
   p.sums = add(2 * 1024 * 8);
   p.scal = add(S_COUNT * 8);
-  p.status = add(16 * 4);
+  p.status = add(16 * 4);  // directly after scal (S_COUNT * 8 is a multiple of ALIGN): one copy reads both
+  static_assert((S_COUNT * 8) % ALIGN == 0, "status must follow the scalar block");
   p.tdc = 0;
   p.total = off;
   return p;
@@ -579,29 +580,31 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful) {
       c->ybeta_dt = P.dt;
     }
   } else {
-    // Each mode's first main-stream kernel is queued before the side stream's
-    // inverse launches, so the main queue never waits on the host issuing them.
+    // The inverse may start with the mode's first main-stream kernel (the
+    // fork mark), but its ~20 launches are issued by the host only after the
+    // mode's first two main-stream kernels are queued, so the main queue does
+    // not wait on the host issuing them.
     mark_fork(c);
     compute_tau(c, P);
-    fork_inverse(c, 2);
     if (!c->ybeta_valid || c->ybeta_dt != P.dt) compute_Y(c, P, 3, p.Yb);
     compute_Z(c, P, 2);
+    fork_inverse(c, 2);
     compute_M(c, P);
     join_inverse(c);
     apply_inverse(c, 2);
     mark_fork(c);
     compute_Y(c, P, 2, p.Ya);
-    fork_inverse(c, 3);
     compute_Z(c, P, 3);
+    fork_inverse(c, 3);
     compute_M(c, P);
     join_inverse(c);
     apply_inverse(c, 3);
     mark_fork(c);
     compute_Y(c, P, 3, p.Yb);
-    fork_inverse(c, 0);
     c->ybeta_valid = true;
     c->ybeta_dt = P.dt;
     compute_G(c, P);
+    fork_inverse(c, 0);
     compute_H(c, P);
     compute_occ(c, 0);
     join_inverse(c);
@@ -891,18 +894,18 @@ CPPPL_API cpppl_status cpppl_create(const cpppl_dims* dims, cpppl_precision prec
   c->stream = (hipStream_t)hip_stream;
   c->plan = build_plan(*dims, prec);
   if (hipSetDevice(device) != hipSuccess ||
-      hipHostMalloc((void**)&c->host_scal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->host_status, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->host_scal, S_COUNT * sizeof(double) + 16 * sizeof(int),
+                    hipHostMallocDefault) != hipSuccess ||
       hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming) != hipSuccess) {
     if (c->host_scal) (void)hipHostFree(c->host_scal);
-    if (c->host_status) (void)hipHostFree(c->host_status);
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->ev_main) (void)hipEventDestroy(c->ev_main);
     delete c;
     return CPPPL_E_HIP;
   }
+  c->host_status = (int*)(c->host_scal + S_COUNT);
   *out = c;
   return CPPPL_OK;
 }
@@ -935,7 +938,6 @@ CPPPL_API cpppl_status cpppl_destroy(cpppl_ctx* c) {
   if (c->ev_side) (void)hipEventDestroy(c->ev_side);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->host_scal) (void)hipHostFree(c->host_scal);
-  if (c->host_status) (void)hipHostFree(c->host_status);
   delete c;
   return CPPPL_OK;
 }
@@ -1155,9 +1157,9 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
     snapshot(c);
     zero_ints(c->at<int>(p.status), 1, c->stream);
     int retries = sweep(c, P, false);
-    CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(p.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
-    CPPPL_HIP(hipMemcpyAsync(c->host_status, c->at(p.status), 16 * sizeof(int), hipMemcpyDeviceToHost,
-                             c->stream));
+    // scalars and status in one copy (status directly follows the scalar block)
+    CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(p.scal), S_COUNT * 8 + 16 * sizeof(int),
+                             hipMemcpyDeviceToHost, c->stream));
     sync(c);
     if (c->host_status[0]) {  // a Cholesky pivot failed: redo this sweep with ridge retries
       restore_snapshot(c);

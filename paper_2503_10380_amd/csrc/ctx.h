@@ -88,8 +88,8 @@ struct cpppl_ctx {
   hipEvent_t ev_main = nullptr, ev_side = nullptr;
   double* inv = nullptr;          // buffer holding -W^{-1} of the last prepared mode
 
-  double* host_scal = nullptr;  // pinned, S_COUNT doubles
-  int* host_status = nullptr;   // pinned, 16 ints
+  double* host_scal = nullptr;  // pinned: S_COUNT doubles followed by the 16 status ints
+  int* host_status = nullptr;   // = (int*)(host_scal + S_COUNT)
 
   // timing
   bool timing = false;

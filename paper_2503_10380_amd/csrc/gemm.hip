@@ -398,17 +398,10 @@ void gemm_bf16_kernel(const KArgs a) {
     if constexpr (B8) T8::store(r8, Bs, tid);
     else TB::store(rb, Bs, tid);
   }
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt & 1);
-    const bf16_t* Ac = As + cur * AS;
-    const bf16_t* Bc = Bs + cur * BS;
-    if (kt + 1 < nk) {
-      const int64_t k1 = kbeg + (kt + 1) * BBK;
-      TA::load(ra, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
-      if constexpr (B8) T8::load(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, k1, kend, vec, a, tid);
-      else TB::load(rb, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
-    }
+  // Long K slices (two work-groups per CU) keep a second register stage so the
+  // global loads of slice k + 2 are in flight while slice k is multiplied.
+  constexpr bool DEEP = BBK == BBK_LONG && !B8;
+  auto mma = [&](const bf16_t* Ac, const bf16_t* Bc) {
 #pragma unroll
     for (int ks = 0; ks < BBK; ks += 32) {
       bf16x8_t af[TM], bfr[TN];
@@ -422,12 +415,55 @@ void gemm_bf16_kernel(const KArgs a) {
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
     }
+  };
+  if constexpr (DEEP) {
+    uint4 ra2[TA::C], rb2[TB::C];
+    if (nk > 1) {
+      TA::load(ra2, A, sa_row, sa_k, m0, a.M, kbeg + BBK, kend, vec, tid);
+      TB::load(rb2, B, sb_row, sb_k, n0, a.N, kbeg + BBK, kend, vec, tid);
+    }
+    __syncthreads();
+    // slice kt sits in LDS buffer kt % 2; register stage kt % 2 is free and
+    // receives slice kt + 2; stage (kt + 1) % 2 holds slice kt + 1
+    auto step = [&](int64_t kt, uint4 (&la)[TA::C], uint4 (&lb)[TB::C], uint4 (&sa)[TA::C],
+                    uint4 (&sb)[TB::C]) {
+      const int cur = (int)(kt & 1);
+      if (kt + 2 < nk) {
+        const int64_t k2 = kbeg + (kt + 2) * BBK;
+        TA::load(la, A, sa_row, sa_k, m0, a.M, k2, kend, vec, tid);
+        TB::load(lb, B, sb_row, sb_k, n0, a.N, k2, kend, vec, tid);
+      }
+      mma(As + cur * AS, Bs + cur * BS);
+      if (kt + 1 < nk) {
+        TA::store(sa, As + (cur ^ 1) * AS, tid);
+        TB::store(sb, Bs + (cur ^ 1) * BS, tid);
+      }
+      __syncthreads();
+    };
+    for (int64_t kt = 0; kt < nk; kt += 2) {
+      step(kt, ra, rb, ra2, rb2);
+      if (kt + 1 < nk) step(kt + 1, ra2, rb2, ra, rb);
+    }
+  } else {
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    const bf16_t* Ac = As + cur * AS;
+    const bf16_t* Bc = Bs + cur * BS;
+    if (kt + 1 < nk) {
+      const int64_t k1 = kbeg + (kt + 1) * BBK;
+      TA::load(ra, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
+      if constexpr (B8) T8::load(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, k1, kend, vec, a, tid);
+      else TB::load(rb, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
+    }
+    mma(Ac, Bc);
     if (kt + 1 < nk) {
       TA::store(ra, As + (cur ^ 1) * AS, tid);
       if constexpr (B8) T8::store(r8, Bs + (cur ^ 1) * BS, tid);
       else TB::store(rb, Bs + (cur ^ 1) * BS, tid);
     }
     __syncthreads();
+  }
   }
 
   // The products are formed as C^T = B^T A^T (B fragment first): element (m, n)

@@ -58,6 +58,8 @@ CASES = [
     (64, 64, 16, 1, 1),
     (33, 257, 300, 1, 4),
     (5, 3, 1, 3, 1),
+    (130, 200, 4104, 1, 1),     # BF16: K slices of 64, odd slice count
+    (257, 129, 9000, 2, 2),     # BF16: K slices of 64 per split, ragged tail
 ]
 
 
