@@ -15,6 +15,8 @@ from .ppl import (  # noqa: F401
     df_integrals,
     form_r,
     form_r_einsum,
+    form_r_fulldf,
+    dress,
     form_r_pairs,
     norm_r2_and_energy,
     khatri_rao,

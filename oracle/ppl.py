@@ -27,22 +27,28 @@ def recompute_t(b_full: np.ndarray, e_occ: np.ndarray, e_vir: np.ndarray) -> np.
     return iajb / d
 
 
-def df_integrals(b_vv: np.ndarray, a0: int = 0, a1: int | None = None) -> np.ndarray:
-    """g[a, b, c, d] = (ac|bd) = sum_X B^X_ac B^X_bd for a in [a0, a1)  (eq. SQG)."""
+def df_integrals(b_vv: np.ndarray, a0: int = 0, a1: int | None = None,
+                 b_right: np.ndarray | None = None) -> np.ndarray:
+    """g[a, b, c, d] = (ac|bd) = sum_X B^X_ac B^X_bd for a in [a0, a1)  (eq. SQG).
+
+    With ``b_right`` (the singles-dressed Dbar of eq. dfB) the second factor
+    is b_right^X_bd: g = sum_X B^X_ac Dbar^X_bd."""
     nx, v, _ = b_vv.shape
     a1 = v if a1 is None else a1
     left = b_vv[:, a0:a1, :].reshape(nx, (a1 - a0) * v)      # X x (a, c)
-    right = b_vv.reshape(nx, v * v)                           # X x (b, d)
+    right = (b_vv if b_right is None else b_right).reshape(nx, v * v)   # X x (b, d)
     g = (left.T @ right).reshape(a1 - a0, v, v, v)            # a, c, b, d
     return g.transpose(0, 2, 1, 3)                            # a, b, c, d
 
 
 def form_r(t: np.ndarray, b_vv: np.ndarray, block: int | None = None,
-           ij_rows: slice | None = None) -> np.ndarray:
-    """The DF particle-particle-ladder tensor with no singles (eq. dfB, tau = t, Dbar = D).
+           ij_rows: slice | None = None, b_right: np.ndarray | None = None) -> np.ndarray:
+    """The DF particle-particle-ladder tensor (eq. dfB).
 
-    R_ijab = sum_cd (sum_X B^X_ac B^X_bd) t_ijcd, computed as
+    R_ijab = sum_cd (sum_X B^X_ac Dbar^X_bd) t_ijcd, computed as
     R_mat (o^2 x v^2) = T_mat (o^2 x v^2) . g_mat^T, with g formed in blocks of a.
+    Without singles Dbar = B and t is the doubles amplitude; with singles pass
+    tau as ``t`` and Dbar as ``b_right`` (see ``dress``).
     ``ij_rows`` restricts the computation to a slice of the (i, j) pair rows.
     """
     o, _, v, _ = t.shape
@@ -54,7 +60,7 @@ def form_r(t: np.ndarray, b_vv: np.ndarray, block: int | None = None,
     out = np.empty((tm.shape[0], v, v))
     for a0 in range(0, v, block):
         a1 = min(v, a0 + block)
-        g = df_integrals(b_vv, a0, a1).reshape((a1 - a0) * v, v * v)
+        g = df_integrals(b_vv, a0, a1, b_right).reshape((a1 - a0) * v, v * v)
         out[:, a0:a1, :] = (tm @ g.T).reshape(tm.shape[0], a1 - a0, v)
     if ij_rows is None:
         return out.reshape(o, o, v, v)
@@ -77,9 +83,38 @@ def form_r_pairs(t: np.ndarray, b_vv: np.ndarray, occ: int) -> np.ndarray:
     return out
 
 
-def form_r_einsum(t: np.ndarray, b_vv: np.ndarray) -> np.ndarray:
+def form_r_einsum(t: np.ndarray, b_vv: np.ndarray, b_right: np.ndarray | None = None) -> np.ndarray:
     """Second route to R (tiny sizes only): one einsum over X, c, d."""
-    return np.einsum("xac,xbd,ijcd->ijab", b_vv, b_vv, t, optimize=True)
+    br = b_vv if b_right is None else b_right
+    return np.einsum("xac,xbd,ijcd->ijab", b_vv, br, t, optimize=True)
+
+
+def dress(t2: np.ndarray, t1: np.ndarray, b_full: np.ndarray):
+    """Singles-dressed inputs of the PPL tensor (eq. B, eq. fulldfB and the Dbar
+    definition before eq. dfB), restricted closed shell:
+    tau_ijcd = t_ijcd + t^c_i t^d_j and Dbar^X_bd = D^X_bd - 2 sum_k D^X_bk t^k_d,
+    with t1[i, c] = t^c_i (o x v) and b_full the DF tensor over all n = o + v
+    orbitals (occupied first).  Returns (tau, B_vv, Dbar_vv)."""
+    o = t1.shape[0]
+    b_vv = b_full[:, o:, o:]
+    b_vo = b_full[:, o:, :o]                                  # B^X_bk, b virtual, k occupied
+    tau = t2 + np.einsum("ic,jd->ijcd", t1, t1)
+    dbar = b_vv - 2.0 * np.einsum("xbk,kd->xbd", b_vo, t1)
+    return tau, b_vv, dbar
+
+
+def form_r_fulldf(t2: np.ndarray, t1: np.ndarray, b_full: np.ndarray) -> np.ndarray:
+    """R with singles straight from eq. fulldfB (tiny sizes only), without the
+    Dbar intermediate: sum_cd sum_X (D^aX_c D^bX_d - 2 sum_k D^aX_c D^bX_k t^k_d) tau_ijcd,
+    with the four-index integrals (ac|bd) and (ac|bk) formed explicitly."""
+    o = t1.shape[0]
+    b_vv = b_full[:, o:, o:]
+    b_vo = b_full[:, o:, :o]
+    tau = t2 + t1[:, None, :, None] * t1[None, :, None, :]
+    g_vvvv = np.einsum("xac,xbd->abcd", b_vv, b_vv)          # (ac|bd)
+    g_vvvo = np.einsum("xac,xbk->abck", b_vv, b_vo)          # (ac|bk)
+    gbar = g_vvvv - 2.0 * np.einsum("abck,kd->abcd", g_vvvo, t1)
+    return np.einsum("abcd,ijcd->ijab", gbar, tau)
 
 
 def norm_r2_and_energy(r: np.ndarray, t: np.ndarray):
@@ -111,11 +146,14 @@ def mttkrp(r: np.ndarray, factors, mode: int) -> np.ndarray:
     return unfold(r, mode) @ khatri_rao(*others)
 
 
-def mttkrp_bruteforce(t: np.ndarray, b_vv: np.ndarray, factors, mode: int) -> np.ndarray:
-    """Nested loops over every index, straight from R_ijab = sum_cdX B_ac B_bd t_ijcd.
+def mttkrp_bruteforce(t: np.ndarray, b_vv: np.ndarray, factors, mode: int,
+                      b_right: np.ndarray | None = None) -> np.ndarray:
+    """Nested loops over every index, straight from R_ijab = sum_cdX B_ac Dbar_bd t_ijcd
+    (Dbar = B without singles).
 
     Pure Python; for tiny sizes only (o, v, X, R of a few).
     """
+    br = b_vv if b_right is None else b_right
     gamma, rho, alpha, beta = factors
     o, _, v, _ = t.shape
     nx = b_vv.shape[0]
@@ -131,7 +169,7 @@ def mttkrp_bruteforce(t: np.ndarray, b_vv: np.ndarray, factors, mode: int) -> np
                         for c in range(v):
                             for d in range(v):
                                 for x in range(nx):
-                                    rv += b_vv[x, a, c] * b_vv[x, b, d] * t[i, j, c, d]
+                                    rv += b_vv[x, a, c] * br[x, b, d] * t[i, j, c, d]
                         w = (gamma[i, r], rho[j, r], alpha[a, r], beta[b, r])
                         prod = 1.0
                         for k in range(4):
@@ -142,7 +180,8 @@ def mttkrp_bruteforce(t: np.ndarray, b_vv: np.ndarray, factors, mode: int) -> np
     return out
 
 
-def mttkrp_chain(t: np.ndarray, b_vv: np.ndarray, factors, mode: int) -> np.ndarray:
+def mttkrp_chain(t: np.ndarray, b_vv: np.ndarray, factors, mode: int,
+                 b_right: np.ndarray | None = None) -> np.ndarray:
     """Matrix-free route in the paper's grouping (eq. distribute and eq. foreachr).
 
     Modes a and b: tau_r[c, d] = sum_ij gamma_ir rho_jr t_ijcd; the other
@@ -151,19 +190,21 @@ def mttkrp_chain(t: np.ndarray, b_vv: np.ndarray, factors, mode: int) -> np.ndar
     Modes i and j (the same idea applied to the occupied factors):
     G_r[c, d] = sum_X (sum_a alpha_ar B^X_ac)(sum_b beta_br B^X_bd),
     H[i, j, r] = sum_cd t_ijcd G_r[c, d], then one occupied factor is summed out.
+    With singles the b side carries Dbar (``b_right``) and t is tau.
     """
     gamma, rho, alpha, beta = factors
+    br = b_vv if b_right is None else b_right
     if mode in (2, 3):
         tau = np.einsum("ir,jr,ijcd->rcd", gamma, rho, t)
         if mode == 2:
-            ybeta = np.einsum("br,xbd->rxd", beta, b_vv)
+            ybeta = np.einsum("br,xbd->rxd", beta, br)
             z = np.einsum("rxd,rcd->rxc", ybeta, tau)
             return np.einsum("xac,rxc->ar", b_vv, z)
         yalpha = np.einsum("ar,xac->rxc", alpha, b_vv)
         z = np.einsum("rxc,rcd->rxd", yalpha, tau)
-        return np.einsum("xbd,rxd->br", b_vv, z)
+        return np.einsum("xbd,rxd->br", br, z)
     yalpha = np.einsum("ar,xac->rxc", alpha, b_vv)
-    ybeta = np.einsum("br,xbd->rxd", beta, b_vv)
+    ybeta = np.einsum("br,xbd->rxd", beta, br)
     g = np.einsum("rxc,rxd->rcd", yalpha, ybeta)
     h = np.einsum("ijcd,rcd->ijr", t, g)
     if mode == 0:
@@ -201,15 +242,16 @@ def energy_cp(t: np.ndarray, factors, lam) -> float:
     return float(np.sum(lam * np.sum(p * q, axis=0)))
 
 
-def rank1_closed_form(u, w, p, q, b_vv):
-    """R for T2 = u_i w_j p_c q_d, in closed CP form of rank X.
+def rank1_closed_form(u, w, p, q, b_vv, b_right=None):
+    """R for T2 (or tau) = u_i w_j p_c q_d, in closed CP form of rank X.
 
-    R_ijab = u_i w_j sum_X (B^X p)_a (B^X q)_b, so R = CP with factors
-    (u 1^T, w 1^T, P, Q), P[a, X] = sum_c B^X_ac p_c, Q[b, X] = sum_d B^X_bd q_d.
+    R_ijab = u_i w_j sum_X (B^X p)_a (Dbar^X q)_b, so R = CP with factors
+    (u 1^T, w 1^T, P, Q), P[a, X] = sum_c B^X_ac p_c, Q[b, X] = sum_d Dbar^X_bd q_d
+    (Dbar = B without singles).
     """
     nx = b_vv.shape[0]
     pm = np.einsum("xac,c->ax", b_vv, p)
-    qm = np.einsum("xbd,d->bx", b_vv, q)
+    qm = np.einsum("xbd,d->bx", b_vv if b_right is None else b_right, q)
     return (np.outer(u, np.ones(nx)), np.outer(w, np.ones(nx)), pm, qm)
 
 

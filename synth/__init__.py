@@ -15,4 +15,6 @@ from .generator import (  # noqa: F401
     perturbation,
     amplitude_sequence,
     rank1_t2,
+    make_singles,
+    rank1_singles,
 )

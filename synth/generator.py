@@ -33,6 +33,7 @@ PURPOSE_INIT = 2
 PURPOSE_PLANTED = 3
 PURPOSE_PERTURB = 4
 PURPOSE_RANK1 = 5
+PURPOSE_SINGLES = 6
 
 
 @dataclass(frozen=True)
@@ -116,6 +117,26 @@ def make_inputs(cfg: Config, seed: int = 0) -> Inputs:
     t = mp2_amplitudes(b_full, e_occ, e_vir)
     b_vv = np.ascontiguousarray(b_full[:, cfg.o:, cfg.o:])
     return Inputs(cfg, b_full, e_occ, e_vir, b_vv, t)
+
+
+def make_singles(inp: "Inputs", seed: int = 0, scale: float = 0.05):
+    """Synthetic singles amplitudes t1[i, a] = scale g_ia / (e_i - e_a), g ~ N(0, 1)
+    (first-order-like size, |t1| ~ 1e-2), and the DF block B^X_ak (virtual a,
+    occupied k) the dressed operand needs.  Returns (t1 (o x v), b_vo (X x v x o))."""
+    cfg = inp.cfg
+    rng = _rng(cfg.cfg_id, PURPOSE_SINGLES, 0, seed)
+    g = rng.standard_normal((cfg.o, cfg.v))
+    t1 = scale * g / (inp.e_occ[:, None] - inp.e_vir[None, :])
+    b_vo = np.ascontiguousarray(inp.b_full[:, cfg.o:, :cfg.o])
+    return t1, b_vo
+
+
+def rank1_singles(cfg: Config, seed: int = 0):
+    """t1 = u p^T with u (o), p (v) ~ N(0, 1): with t2 = 0, tau = u u p p is rank one."""
+    rng = _rng(cfg.cfg_id, PURPOSE_SINGLES, 1, seed)
+    u = rng.standard_normal(cfg.o)
+    p = rng.standard_normal(cfg.v)
+    return np.outer(u, p), (u, p)
 
 
 def init_factors(cfg: Config, rank: int | None = None, seed: int = 0, k: int = 0):
