@@ -68,6 +68,8 @@ typedef struct {
   int64_t v;    /* virtual orbitals (a, b, c, d) */
   int64_t nx;   /* density-fitting auxiliary functions X */
   int64_t rank; /* CP rank R, 1 <= R <= 4096 */
+  int64_t singles; /* non-zero: reserve room for the singles-dressed operands
+                      (cpppl_load_singles); 0: doubles only */
 } cpppl_dims;
 
 typedef struct {
@@ -168,6 +170,22 @@ CPPPL_API cpppl_status cpppl_get_factors(cpppl_ctx* ctx, double* fi, double* fj,
                                          double* fb, double* lam, int on_device);
 
 /* ---- work ---------------------------------------------------------------------- */
+
+/* Singles (T1) dressing of the PPL tensor (Section "The Density Fitting
+ * approximation": eq. B, eq. fulldfB and the Dbar intermediate of eq. dfB).
+ * t1 is o x v row-major with t1[i][a] = t^a_i; b_vo is X x v x o row-major with
+ * b_vo[X][a][k] = D^{aX}_k, the virtual-occupied block of the DF tensor.  The
+ * context then contracts tau_ijcd = t_ijcd + t1[i][c] t1[j][d] in place of t
+ * and Dbar^X_bd = D^X_bd - 2 sum_k D^X_bk t1[k][d] on the b side (alpha keeps
+ * D):  R_ijab = sum_cd (sum_X D^X_ac Dbar^X_bd) tau_ijcd.  The dressing stays
+ * with the context: later cpppl_load_t2 / cpppl_load_df calls are dressed with
+ * the same t1, and cpppl_warm_start's dt is added to the doubles part.  ||R||^2
+ * and E_exact become those of the dressed tensor, and E_CP = sum CP tau.
+ * t1 == NULL removes the dressing (b_vo is then ignored).  Needs dims.singles
+ * != 0 (E_UNSUPPORTED otherwise) and t2 and the DF tensor loaded (E_STATE);
+ * not available for planted tensors.  on_device: pointers are device memory. */
+CPPPL_API cpppl_status cpppl_load_singles(cpppl_ctx* ctx, const double* t1, const double* b_vo,
+                                          int on_device);
 
 /* Run ALS sweeps (order alpha, beta, gamma, rho) from the current factors. */
 CPPPL_API cpppl_status cpppl_als(cpppl_ctx* ctx, const cpppl_als_opts* opts,

@@ -33,7 +33,8 @@ class CppplError(RuntimeError):
 
 
 class Dims(C.Structure):
-    _fields_ = [("o", C.c_int64), ("v", C.c_int64), ("nx", C.c_int64), ("rank", C.c_int64)]
+    _fields_ = [("o", C.c_int64), ("v", C.c_int64), ("nx", C.c_int64), ("rank", C.c_int64),
+                ("singles", C.c_int64)]
 
 
 class AlsOpts(C.Structure):
@@ -83,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "cpppl_destroy": (st, [_P]),
         "cpppl_load_t2": (st, [_P, _P, C.c_int]),
         "cpppl_load_df": (st, [_P, _P, C.c_int]),
+        "cpppl_load_singles": (st, [_P, _P, _P, C.c_int]),
         "cpppl_load_planted": (st, [_P, _P, _P, _P, _P, _P, C.c_int64, C.c_int]),
         "cpppl_norm_r2": (st, [_P, _D, _D]),
         "cpppl_set_factors": (st, [_P, _P, _P, _P, _P, _P, C.c_int]),
@@ -141,10 +143,10 @@ class Context:
     contiguous); results come back as numpy arrays.
     """
 
-    def __init__(self, o, v, nx, rank, precision="fp64", device=0, stream=None):
+    def __init__(self, o, v, nx, rank, precision="fp64", device=0, stream=None, singles=False):
         torch = _torch()
         self.lib = load_library()
-        self.dims = Dims(o, v, nx, rank)
+        self.dims = Dims(o, v, nx, rank, 1 if singles else 0)
         self.o, self.v, self.nx, self.rank = o, v, nx, rank
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.device = device
@@ -213,6 +215,19 @@ class Context:
         keep = []
         p, dev = self._arg(b, (self.nx, self.v, self.v), keep)
         self._call("cpppl_load_df", p, dev)
+
+    def load_singles(self, t1, b_vo):
+        """Dress the PPL tensor with singles t1 (o x v) and the DF block
+        b_vo (X x v x o); t1=None removes the dressing."""
+        keep = []
+        if t1 is None:
+            self._call("cpppl_load_singles", None, None, 0)
+            return
+        p1, d1 = self._arg(t1, (self.o, self.v), keep)
+        p2, d2 = self._arg(b_vo, (self.nx, self.v, self.o), keep)
+        if d1 != d2:
+            raise ValueError("t1 and b_vo must both be on the host or both on the device")
+        self._call("cpppl_load_singles", p1, p2, d1)
 
     def load_planted(self, fi, fj, fa, fb, lam=None):
         rp = np.shape(fi)[1]

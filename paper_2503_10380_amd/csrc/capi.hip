@@ -70,6 +70,19 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   p.sT = f8 ? add((size_t)(o * o) * 4) : 0;
   p.sB = f8 ? add((size_t)X * 4) : 0;
   p.sBx = f8 ? add((size_t)(X * v) * 4) : 0;
+  const bool sg = d.singles != 0;
+  p.t2raw = sg ? add(o2v2 * 8) : 0;
+  p.t1 = sg ? add((size_t)(o * v) * 8) : 0;
+  p.bvo = sg ? add((size_t)(X * v * o) * 8) : 0;
+  p.bb64 = sg ? add(xv2 * 8) : 0;
+  p.bb64T = sg ? add(xv2 * 8) : 0;
+  p.bb64P = sg ? add(xv2 * 8) : 0;
+  p.bb16T = (sg && bf) ? add(xv2 * 2) : 0;
+  p.bb16P = (sg && bf) ? add(xv2 * 2) : 0;
+  p.bb8T = (sg && f8) ? add(xv2) : 0;
+  p.bb8P = (sg && f8) ? add(xv2) : 0;
+  p.sBb = (sg && f8) ? add((size_t)X * 4) : 0;
+  p.sBbx = (sg && f8) ? add((size_t)(X * v) * 4) : 0;
   for (int m = 0; m < 4; ++m) {
     const size_t n = (size_t)nmode(d, m);
     p.FT[m] = add(n * R * 8);
@@ -181,6 +194,8 @@ Path path_for(cpppl_ctx* c, DType dt) {
     P.T2T = c->at(p.t64T);
     P.BnT = c->at(p.b64T);
     P.Bp = c->at(p.b64P);
+    P.BnT_b = c->singles_on ? c->at(p.bb64T) : P.BnT;
+    P.Bp_b = c->singles_on ? c->at(p.bb64P) : P.Bp;
     for (int m = 0; m < 4; ++m) P.FTop[m] = c->at(p.FT[m]);
   } else if (c->prec == CPPPL_BF16) {
     P.esz = 2;
@@ -188,6 +203,8 @@ Path path_for(cpppl_ctx* c, DType dt) {
     P.T2T = c->at(p.t16T);
     P.BnT = c->at(p.b16T);
     P.Bp = c->at(p.b16P);
+    P.BnT_b = c->singles_on ? c->at(p.bb16T) : P.BnT;
+    P.Bp_b = c->singles_on ? c->at(p.bb16P) : P.Bp;
     for (int m = 0; m < 4; ++m) P.FTop[m] = c->at(p.F16T[m]);
   } else if (c->prec == CPPPL_FP8_E4M3) {
     // e4m3 t and B (scaled per ij row and per X slice), bfloat16 everything else
@@ -199,6 +216,9 @@ Path path_for(cpppl_ctx* c, DType dt) {
     P.Bp = c->at(p.b8P);
     P.sT = c->at<float>(p.sT);
     P.sBx = c->at<float>(p.sBx);
+    P.BnT_b = c->singles_on ? c->at(p.bb8T) : P.BnT;
+    P.Bp_b = c->singles_on ? c->at(p.bb8P) : P.Bp;
+    P.sBx_b = c->singles_on ? c->at<float>(p.sBbx) : P.sBx;
     for (int m = 0; m < 4; ++m) P.FTop[m] = c->at(p.F16T[m]);
   } else {
     throw StatusError(CPPPL_E_UNSUPPORTED, "the low-precision path needs a BF16 or FP8 context");
@@ -236,15 +256,17 @@ void compute_tau(cpppl_ctx* c, const Path& P) {
   run_gemm(P, g, c->stream);
 }
 
-// Y[r][X][q] = sum_p F[r][p] B^X_pq for F = factor `mode` (2 alpha, 3 beta)
+// Y[r][X][q] = sum_p F[r][p] B^X_pq for F = factor `mode` (2 alpha with B,
+// 3 beta with the b-side operand: Dbar with singles, eq. dfB)
 void compute_Y(cpppl_ctx* c, const Path& P, int mode, size_t out) {
   Span sp(c, CPPPL_T_Y);
   const int64_t v = c->d.v, X = c->d.nx, R = c->d.rank;
+  const bool bside = mode == 3;
   Gemm g;
   g.M = R; g.N = X * v; g.K = v;
   g.A = P.FTop[mode]; g.sam = v; g.sak = 1;
-  g.B = P.BnT; g.sbn = v; g.sbk = 1;
-  g.b_fp8 = P.fp8; g.bscale = P.sBx; g.bscale_mode = 1;  // n = (X, q)
+  g.B = bside ? P.BnT_b : P.BnT; g.sbn = v; g.sbk = 1;
+  g.b_fp8 = P.fp8; g.bscale = bside ? P.sBx_b : P.sBx; g.bscale_mode = 1;  // n = (X, q)
   g.C = c->at(out); g.scm = X * v; g.ctype = P.dt;
   run_gemm(P, g, c->stream);
 }
@@ -262,15 +284,17 @@ void compute_Z(cpppl_ctx* c, const Path& P, int mode) {
   run_gemm(P, g, c->stream);
 }
 
-// M^T[r][p] = sum_{X,q} Z[r][X][q] B^X_pq  -> MT (FP64)
-void compute_M(cpppl_ctx* c, const Path& P) {
+// M^T[r][p] = sum_{X,q} Z[r][X][q] B^X_pq  -> MT (FP64); mode 3 (beta)
+// contracts the b-side operand (Dbar with singles)
+void compute_M(cpppl_ctx* c, const Path& P, int mode) {
   Span sp(c, CPPPL_T_M);
   const int64_t v = c->d.v, X = c->d.nx, R = c->d.rank;
+  const bool bside = mode == 3;
   Gemm g;
   g.M = R; g.N = v; g.K = X * v;
   g.A = c->at(c->plan.Z); g.sam = X * v; g.sak = 1;
-  g.B = P.Bp; g.sbn = X * v; g.sbk = 1;
-  g.b_fp8 = P.fp8; g.bscale = P.sBx; g.bscale_mode = 2;  // k = (X, q), v % 8 == 0
+  g.B = bside ? P.Bp_b : P.Bp; g.sbn = X * v; g.sbk = 1;
+  g.b_fp8 = P.fp8; g.bscale = bside ? P.sBx_b : P.sBx; g.bscale_mode = 2;  // k = (X, q), v % 8 == 0
   g.C = c->at(c->plan.MT); g.scm = v; g.ctype = DType::F64;
   g.splits = splits_for(c, P, g.M, g.N, g.K, 1);
   g.partial = c->at(c->plan.partial);
@@ -450,7 +474,7 @@ void mttkrp_into_MT(cpppl_ctx* c, const Path& P, int mode) {
     if (mode == 2) compute_Y(c, P, 3, c->plan.Yb);
     else compute_Y(c, P, 2, c->plan.Ya);
     compute_Z(c, P, mode);
-    compute_M(c, P);
+    compute_M(c, P, mode);
   } else {
     compute_Y(c, P, 2, c->plan.Ya);
     compute_Y(c, P, 3, c->plan.Yb);
@@ -563,11 +587,11 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful) {
       compute_tau(c, P);
       if (!c->ybeta_valid || c->ybeta_dt != P.dt) compute_Y(c, P, 3, p.Yb);
       compute_Z(c, P, 2);
-      compute_M(c, P);
+      compute_M(c, P, 2);
       retries += solve_mode(c, 2, true);
       compute_Y(c, P, 2, p.Ya);
       compute_Z(c, P, 3);
-      compute_M(c, P);
+      compute_M(c, P, 3);
       retries += solve_mode(c, 3, true);
       compute_Y(c, P, 3, p.Yb);
       compute_G(c, P);
@@ -589,14 +613,14 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful) {
     if (!c->ybeta_valid || c->ybeta_dt != P.dt) compute_Y(c, P, 3, p.Yb);
     compute_Z(c, P, 2);
     fork_inverse(c, 2);
-    compute_M(c, P);
+    compute_M(c, P, 2);
     join_inverse(c);
     apply_inverse(c, 2);
     mark_fork(c);
     compute_Y(c, P, 2, p.Ya);
     compute_Z(c, P, 3);
     fork_inverse(c, 3);
-    compute_M(c, P);
+    compute_M(c, P, 3);
     join_inverse(c);
     apply_inverse(c, 3);
     mark_fork(c);
@@ -665,9 +689,9 @@ void compute_norm_r2(cpppl_ctx* c) {
   zero_doubles(sc + S_NORM_R2, 2, c->stream);
   for (int64_t a0 = 0; a0 < v; a0 += ab) {
     const int64_t nb = std::min(ab, v - a0);
-    Gemm g1;  // g_a[(b,d)][c] = sum_X B[X][(b,d)] B[X][a][c]
+    Gemm g1;  // g_a[(b,d)][c] = sum_X Dbar[X][(b,d)] B[X][a][c]   (Dbar = B without singles)
     g1.batch = nb; g1.M = v2; g1.N = v; g1.K = X;
-    g1.A = c->at(p.b64); g1.sam = 1; g1.sak = v2; g1.sab = 0;
+    g1.A = c->at(c->singles_on ? p.bb64 : p.b64); g1.sam = 1; g1.sak = v2; g1.sab = 0;
     g1.B = c->at<double>(p.b64) + a0 * v; g1.sbk = v2; g1.sbn = 1; g1.sbb = v;
     g1.C = gblk; g1.scm = v; g1.scb = v * v2; g1.ctype = DType::F64;
     gemm_f64(g1, c->stream);
@@ -739,6 +763,58 @@ void derive_t(cpppl_ctx* c) {
   }
 }
 
+// Layouts of a DF-type operand (B, or Dbar with singles) from its FP64 master
+// src[X][p][q]: B^X transposed per X and the (p, X, q) permutation, in FP64 and
+// in the context's low precision (e4m3 with one power-of-two scale per X).
+struct BLayouts {
+  size_t f64T, f64P, bf16T, bf16P, e4T, e4P, scale, scale_x;
+};
+void derive_b(cpppl_ctx* c, size_t src, const BLayouts& L) {
+  const int64_t v = c->d.v, X = c->d.nx, n = X * v * v;
+  const double* b = c->at<double>(src);
+  transpose_batched(b, c->at(L.f64T), DType::F64, X, v, v, c->stream);
+  permute_pxq(b, c->at(L.f64P), DType::F64, X, v, c->stream);
+  if (c->prec == CPPPL_BF16) {
+    transpose_batched(b, c->at(L.bf16T), DType::BF16, X, v, v, c->stream);
+    permute_pxq(b, c->at(L.bf16P), DType::BF16, X, v, c->stream);
+  } else if (c->prec == CPPPL_FP8_E4M3) {
+    float* sc = c->at<float>(L.scale);
+    e4m3_row_scales(b, X, v * v, sc, c->stream);
+    quantize_e4m3(c->at<double>(L.f64T), c->at<uint8_t>(L.e4T), n, sc, v * v, X, 1, c->stream);
+    quantize_e4m3(c->at<double>(L.f64P), c->at<uint8_t>(L.e4P), n, sc, 1, X * v, v, c->stream);
+    expand_scales(sc, c->at<float>(L.scale_x), X, v, c->stream);
+  }
+}
+
+// t64 from the raw doubles: tau = t2 + t1 t1 with singles (eq. B), else t2.
+void dress_t(cpppl_ctx* c) {
+  const Plan& p = c->plan;
+  const int64_t o = c->d.o, v = c->d.v;
+  if (c->singles_on)
+    dress_tau(c->at<double>(p.t2raw), c->at<double>(p.t1), c->at<double>(p.t64), o, v, c->stream);
+  else
+    CPPPL_HIP(hipMemcpyAsync(c->at(p.t64), c->at(p.t2raw), (size_t)(o * o * v * v) * 8,
+                             hipMemcpyDeviceToDevice, c->stream));
+  derive_t(c);
+}
+
+// Dbar^X_bd = D^X_bd - 2 sum_k D^X_bk t1[k][d] (the intermediate before eq. dfB)
+// and its layouts.
+void derive_dbar(cpppl_ctx* c) {
+  const Plan& p = c->plan;
+  const int64_t o = c->d.o, v = c->d.v, X = c->d.nx;
+  CPPPL_HIP(hipMemcpyAsync(c->at(p.bb64), c->at(p.b64), (size_t)(X * v * v) * 8,
+                           hipMemcpyDeviceToDevice, c->stream));
+  Gemm g;  // per X: Dbar[b][d] += -2 sum_k bvo[b][k] t1[k][d]
+  g.batch = X; g.M = v; g.N = v; g.K = o;
+  g.A = c->at(p.bvo); g.sam = o; g.sak = 1; g.sab = v * o;
+  g.B = c->at(p.t1); g.sbk = v; g.sbn = 1; g.sbb = 0;
+  g.C = c->at(p.bb64); g.scm = v; g.scb = v * v; g.ctype = DType::F64;
+  g.alpha = -2.0; g.beta = 1.0;
+  gemm_f64(g, c->stream);
+  derive_b(c, p.bb64, BLayouts{p.bb64T, p.bb64P, p.bb16T, p.bb16P, p.bb8T, p.bb8P, p.sBb, p.sBbx});
+}
+
 void init_after_factors(cpppl_ctx* c) {
   for (int m = 0; m < 4; ++m) {
     compute_gram(c, m);
@@ -802,6 +878,12 @@ double ws_judge_loss(cpppl_ctx* c) {
   CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(p.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
   sync(c);
   return c->host_scal[S_JUDGE + 1] - 2.0 * c->host_scal[S_JUDGE];
+}
+void ws_add_dt(cpppl_ctx* c) {
+  const Plan& p = c->plan;
+  const int64_t n = c->d.o * c->d.o * c->d.v * c->d.v;
+  axpy1(c->at<double>(p.dt64), c->at<double>(p.t64), n, c->stream);
+  if (c->d.singles) axpy1(c->at<double>(p.dt64), c->at<double>(p.t2raw), n, c->stream);
 }
 void ws_derive_t(cpppl_ctx* c) {
   derive_t(c);
@@ -947,11 +1029,44 @@ CPPPL_API cpppl_status cpppl_load_t2(cpppl_ctx* c, const double* t, int on_devic
   need_ws(c);
   if (!t) throw std::invalid_argument("t is NULL");
   const int64_t n = c->d.o * c->d.o * c->d.v * c->d.v;
-  load_device_or_host(c, c->at(c->plan.t64), t, (size_t)n * 8, on_device);
-  check_finite_input(c, c->at<double>(c->plan.t64), n, "t2");
-  derive_t(c);
+  if (c->d.singles) {  // keep the raw doubles; t64 holds what the chain contracts
+    load_device_or_host(c, c->at(c->plan.t2raw), t, (size_t)n * 8, on_device);
+    check_finite_input(c, c->at<double>(c->plan.t2raw), n, "t2");
+    dress_t(c);
+  } else {
+    load_device_or_host(c, c->at(c->plan.t64), t, (size_t)n * 8, on_device);
+    check_finite_input(c, c->at<double>(c->plan.t64), n, "t2");
+    derive_t(c);
+  }
   c->have_t = true;
   c->planted = false;
+  c->norm_valid = false;
+  c->ybeta_valid = false;
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_load_singles(cpppl_ctx* c, const double* t1, const double* b_vo,
+                                          int on_device) {
+  API_TRY(c)
+  need_ws(c);
+  if (!c->d.singles)
+    throw StatusError(CPPPL_E_UNSUPPORTED, "context created without room for singles (dims.singles = 0)");
+  if (c->planted) throw StatusError(CPPPL_E_STATE, "no singles dressing for a planted tensor");
+  if (!c->have_t || !c->have_b) throw StatusError(CPPPL_E_STATE, "load t2 and the DF tensor first");
+  const Plan& p = c->plan;
+  const int64_t o = c->d.o, v = c->d.v, X = c->d.nx;
+  if (t1) {
+    if (!b_vo) throw std::invalid_argument("b_vo is NULL");
+    load_device_or_host(c, c->at(p.t1), t1, (size_t)(o * v) * 8, on_device);
+    load_device_or_host(c, c->at(p.bvo), b_vo, (size_t)(X * v * o) * 8, on_device);
+    check_finite_input(c, c->at<double>(p.t1), o * v, "t1");
+    check_finite_input(c, c->at<double>(p.bvo), X * v * o, "the virtual-occupied DF block");
+    c->singles_on = true;
+    derive_dbar(c);
+  } else {
+    c->singles_on = false;
+  }
+  dress_t(c);
   c->norm_valid = false;
   c->ybeta_valid = false;
   API_CATCH(c)
@@ -965,18 +1080,8 @@ CPPPL_API cpppl_status cpppl_load_df(cpppl_ctx* c, const double* b, int on_devic
   const Plan& p = c->plan;
   load_device_or_host(c, c->at(p.b64), b, (size_t)n * 8, on_device);
   check_finite_input(c, c->at<double>(p.b64), n, "the DF tensor");
-  transpose_batched(c->at<double>(p.b64), c->at(p.b64T), DType::F64, X, v, v, c->stream);
-  permute_pxq(c->at<double>(p.b64), c->at(p.b64P), DType::F64, X, v, c->stream);
-  if (c->prec == CPPPL_BF16) {
-    transpose_batched(c->at<double>(p.b64), c->at(p.b16T), DType::BF16, X, v, v, c->stream);
-    permute_pxq(c->at<double>(p.b64), c->at(p.b16P), DType::BF16, X, v, c->stream);
-  } else if (c->prec == CPPPL_FP8_E4M3) {
-    float* sB = c->at<float>(p.sB);
-    e4m3_row_scales(c->at<double>(p.b64), X, v * v, sB, c->stream);
-    quantize_e4m3(c->at<double>(p.b64T), c->at<uint8_t>(p.b8T), n, sB, v * v, X, 1, c->stream);
-    quantize_e4m3(c->at<double>(p.b64P), c->at<uint8_t>(p.b8P), n, sB, 1, X * v, v, c->stream);
-    expand_scales(sB, c->at<float>(p.sBx), X, v, c->stream);
-  }
+  derive_b(c, p.b64, BLayouts{p.b64T, p.b64P, p.b16T, p.b16P, p.b8T, p.b8P, p.sB, p.sBx});
+  if (c->singles_on) derive_dbar(c);
   c->have_b = true;
   c->planted = false;
   c->norm_valid = false;

@@ -20,6 +20,9 @@ struct Plan {
   // e4m3 operand copies and their power-of-two scales (FP8 contexts): sT per ij,
   // sB per X, sBx[X*v + q] = sB[X]
   size_t t8, t8T, b8T, b8P, sT, sB, sBx;
+  // singles (dims.singles): raw doubles t2 (t64 then holds tau), t1, D_vo, and
+  // Dbar with the same layouts and copies as B
+  size_t t2raw, t1, bvo, bb64, bb64T, bb64P, bb16T, bb16P, bb8T, bb8P, sBb, sBbx;
   // factors (transposed, R x n), weights, snapshots, Grams
   size_t FT[4], FTprev[4], F16T[4], lam, lamprev;
   size_t gram[4], cross[4], invA, invB, invD, MT, stage, nearRing, nearCache;
@@ -56,8 +59,11 @@ struct Path {
   const float* sBx = nullptr;  // scale of B^X, repeated per (X, q)
   const void* T2;   // t[ij][cd]   (o^2 x v^2)
   const void* T2T;  // t[cd][ij]   (v^2 x o^2)
-  const void* BnT;  // B[X][q][p]  = B^X_pq
+  const void* BnT;  // B[X][q][p]  = B^X_pq       (alpha side)
   const void* Bp;   // B[p][X][q]  = B^X_pq
+  const void* BnT_b;  // the same layouts of the b-side operand: Dbar with singles, else B
+  const void* Bp_b;
+  const float* sBx_b = nullptr;  // its e4m3 scales
   const void* FTop[4];
 };
 
@@ -76,6 +82,7 @@ struct cpppl_ctx {
   cpppl::Plan plan;
 
   bool have_t = false, have_b = false, have_factors = false, planted = false;
+  bool singles_on = false;  // t64 holds tau and the b side uses Dbar
   int64_t rank_p = 0;
   bool norm_valid = false;
   bool ybeta_valid = false;

@@ -146,6 +146,17 @@ __global__ void expand_scales_kernel(const float* __restrict__ sc, float* out, i
     out[i] = sc[i / v];
 }
 
+__global__ void dress_tau_kernel(const double* __restrict__ t2, const double* __restrict__ t1,
+                                 double* tau, int64_t o, int64_t v) {
+  const int64_t n = o * o * v * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ij = e / (v * v), cd = e % (v * v);
+    const int64_t i = ij / o, j = ij % o, cc = cd / v, d = cd % v;
+    tau[e] = t2[e] + t1[i * v + cc] * t1[j * v + d];
+  }
+}
+
 __global__ void hadamard_kernel(const double* __restrict__ g1, const double* __restrict__ g2,
                                 const double* __restrict__ g3, double* w, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -453,6 +464,13 @@ void expand_scales(const float* scale, float* out, int64_t nx, int64_t v, hipStr
   if (nx * v <= 0) return;
   hipLaunchKernelGGL(expand_scales_kernel, dim3(blocks_for(nx * v)), dim3(TPB), 0, s, scale, out, nx, v);
   CPPPL_LAUNCH_CHECK("expand_scales");
+}
+
+void dress_tau(const double* t2, const double* t1, double* tau, int64_t o, int64_t v, hipStream_t s) {
+  const int64_t n = o * o * v * v;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(dress_tau_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, t2, t1, tau, o, v);
+  CPPPL_LAUNCH_CHECK("dress_tau");
 }
 
 void hadamard(const double* g1, const double* g2, const double* g3, double* w, int64_t n,

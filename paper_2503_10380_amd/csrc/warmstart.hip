@@ -161,7 +161,7 @@ CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* c, const double* dt, int on_d
 
   if (strategy == CPPPL_WS_NEAR_OPTIMAL) {  // the cached (n-5)th iterate, no features
     ws_load_dt(c, dt, on_device);
-    axpy1(c->at<double>(p.dt64), c->at<double>(p.t64), c->d.o * c->d.o * c->d.v * c->d.v, c->stream);
+    ws_add_dt(c);
     ws_derive_t(c);
     const bool used = ws_install_near_cache(c);
     c->ws_valid = false;
@@ -208,7 +208,7 @@ CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* c, const double* dt, int on_d
   if (strategy == CPPPL_WS_LEARNED) mlp_forward_dev(mlp, feat, R, c->at<float>(p.wsOut), c->stream);
 
   // the new amplitudes: t <- t + dt
-  axpy1(c->at<double>(p.dt64), c->at<double>(p.t64), c->d.o * c->d.o * c->d.v * c->d.v, c->stream);
+  ws_add_dt(c);
   ws_derive_t(c);
 
   // judge against the plain warm start

@@ -19,6 +19,8 @@ void ws_mttkrp_into_MT(cpppl_ctx* c, DType dt, int mode);
 void ws_solve_no_update(cpppl_ctx* c, int mode, size_t out_off);
 // Grams, low-precision copies and the eta reference after the factors changed.
 void ws_init_after_factors(cpppl_ctx* c);
+// t <- t + dt (the loaded dt; with singles the raw doubles follow, tau = t2 + t1 t1).
+void ws_add_dt(cpppl_ctx* c);
 // Re-derive the operand layouts of t from the FP64 master.
 void ws_derive_t(cpppl_ctx* c);
 void ws_ensure_norm(cpppl_ctx* c);

@@ -58,6 +58,14 @@ def test_workspace_size_host_only(lib):
     c3 = cp.Dims(32, 256, 768, 1024)
     assert lib.cpppl_workspace_size(C.byref(c3), cp.BF16, C.byref(size)) == 0
     assert size.value < 16 * 2 ** 30  # C3 fits comfortably in one GPU's HBM
+    # FP8 needs v % 8 == 0; singles reserve room for tau, t1, D_vo and Dbar
+    assert lib.cpppl_workspace_size(C.byref(d), cp.FP8, C.byref(size)) == 0
+    assert lib.cpppl_workspace_size(C.byref(cp.Dims(4, 12, 48, 32)), cp.FP8, C.byref(size)) == -1
+    for prec in (cp.FP64, cp.BF16, cp.FP8):
+        lib.cpppl_workspace_size(C.byref(d), prec, C.byref(size))
+        plain = size.value
+        lib.cpppl_workspace_size(C.byref(cp.Dims(4, 16, 48, 32, 1)), prec, C.byref(size))
+        assert size.value > plain
 
 
 def test_status_strings_and_null_handling(lib):
