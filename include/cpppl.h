@@ -198,6 +198,15 @@ CPPPL_API cpppl_status cpppl_mttkrp(cpppl_ctx* ctx, int mode, cpppl_precision pr
                                     int on_device);
 /* fit, <R, CP> and ||CP||^2 at the current factors (one FP64 MTTKRP). */
 CPPPL_API cpppl_status cpppl_fit(cpppl_ctx* ctx, double* fit, double* inner, double* cp_norm2);
+/* The CP tensor at the current factors, CP_ijab = sum_r lambda_r gamma_ir rho_jr
+ * alpha_ar beta_br (eq. cp-ppl), formed explicitly in FP64 as one o^2 x v^2 x R
+ * GEMM of two Khatri-Rao products, into out (o x o x v x v row-major, o^2 v^2
+ * doubles, caller-owned; device memory if on_device, else host).  symmetrize
+ * != 0 then replaces it by (CP_ijab + CP_jiba) / 2, the pair symmetry the ALS
+ * does not enforce (Section "The CPD approximation of the PPL tensor-network",
+ * the reconstruction for the rest of the CCSD iteration).  Synchronises; drops
+ * the cached Y_beta. */
+CPPPL_API cpppl_status cpppl_reconstruct(cpppl_ctx* ctx, double* out, int symmetrize, int on_device);
 /* E_CP = sum_ijab CP_ijab t_ijab at the current factors, FP64. */
 CPPPL_API cpppl_status cpppl_energy(cpppl_ctx* ctx, double* e_cp);
 

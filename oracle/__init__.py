@@ -25,6 +25,7 @@ from .ppl import (  # noqa: F401
     mttkrp_bruteforce,
     mttkrp_chain,
     cp_full,
+    symmetrize_pairs,
     cp_norm2,
     cp_inner,
     energy_cp,

@@ -220,6 +220,12 @@ def cp_full(factors, lam=None) -> np.ndarray:
     return np.einsum("r,ir,jr,ar,br->ijab", lam, gamma, rho, alpha, beta, optimize=True)
 
 
+def symmetrize_pairs(x: np.ndarray) -> np.ndarray:
+    """(X_ijab + X_jiba) / 2: the pair symmetry restored after reconstruction
+    (Section "The CPD approximation of the PPL tensor-network")."""
+    return 0.5 * (x + x.transpose(1, 0, 3, 2))
+
+
 def cp_norm2(factors, lam) -> float:
     """||CP||^2 from the Hadamard product of the four Grams (eq. cp_norm2), with weights."""
     w = np.ones((len(lam), len(lam)))

@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "cpppl_mttkrp": (st, [_P, C.c_int, C.c_int, _P, C.c_int]),
         "cpppl_fit": (st, [_P, _D, _D, _D]),
         "cpppl_energy": (st, [_P, _D]),
+        "cpppl_reconstruct": (st, [_P, _P, C.c_int, C.c_int]),
         "cpppl_mlp_create": (st, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_uint64, C.c_int,
                                   C.POINTER(_P)]),
         "cpppl_mlp_destroy": (st, [_P]),
@@ -298,6 +299,18 @@ class Context:
         f, i, c = C.c_double(), C.c_double(), C.c_double()
         self._call("cpppl_fit", C.byref(f), C.byref(i), C.byref(c))
         return f.value, i.value, c.value
+
+    def reconstruct(self, symmetrize=False, out=None):
+        """The CP tensor (o, o, v, v) in FP64, optionally pair-symmetrised; into
+        `out` (a device float64 tensor) when given, else returned as numpy."""
+        if out is not None:
+            keep = []
+            p, dev = self._arg(out, (self.o, self.o, self.v, self.v), keep)
+            self._call("cpppl_reconstruct", p, int(bool(symmetrize)), dev)
+            return out
+        res = np.empty((self.o, self.o, self.v, self.v))
+        self._call("cpppl_reconstruct", _ptr_host(res), int(bool(symmetrize)), 0)
+        return res
 
     def energy(self):
         e = C.c_double()

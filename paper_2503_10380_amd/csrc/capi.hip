@@ -1214,6 +1214,34 @@ CPPPL_API cpppl_status cpppl_fit(cpppl_ctx* c, double* fit, double* inner, doubl
   API_CATCH(c)
 }
 
+CPPPL_API cpppl_status cpppl_reconstruct(cpppl_ctx* c, double* out, int symmetrize, int on_device) {
+  API_TRY(c)
+  need_ws(c);
+  if (!out) throw std::invalid_argument("out is NULL");
+  if (!c->have_factors) throw StatusError(CPPPL_E_STATE, "set the factors first");
+  const Plan& p = c->plan;
+  const int64_t o = c->d.o, v = c->d.v, R = c->d.rank;
+  double* dst = on_device ? out : c->at<double>(p.dt64);  // dt64 stages a host result
+  // KR(gamma, rho) diag(lambda) and KR(alpha, beta), both R x (pairs); the
+  // second lives in the intermediate region, whose cached Y_beta is dropped
+  khatri_rao_t(c->at<double>(p.FT[0]), c->at<double>(p.FT[1]), o, R, c->at(p.Kt), DType::F64,
+               c->stream, nullptr, c->at<double>(p.lam));
+  khatri_rao_t(c->at<double>(p.FT[2]), c->at<double>(p.FT[3]), v, R, c->at(p.big), DType::F64,
+               c->stream);
+  c->ybeta_valid = false;
+  Gemm g;  // CP[ij][ab] = sum_r Kt[r][ij] Ka[r][ab]
+  g.M = o * o; g.N = v * v; g.K = R;
+  g.A = c->at(p.Kt); g.sam = 1; g.sak = o * o;
+  g.B = c->at(p.big); g.sbk = v * v; g.sbn = 1;
+  g.C = dst; g.scm = v * v; g.ctype = DType::F64;
+  gemm_f64(g, c->stream);
+  if (symmetrize) symmetrize_pairs(dst, o, v, c->stream);
+  if (!on_device)
+    CPPPL_HIP(hipMemcpyAsync(out, dst, (size_t)(o * o * v * v) * 8, hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  API_CATCH(c)
+}
+
 CPPPL_API cpppl_status cpppl_energy(cpppl_ctx* c, double* e_cp) {
   API_TRY(c)
   if (!e_cp) throw std::invalid_argument("e_cp is NULL");

@@ -21,9 +21,12 @@ void permute_pxq(const double* b, void* out, DType ot, int64_t nx, int64_t v, hi
 void convert(const double* x, void* y, DType yt, int64_t n, hipStream_t s);
 // y[i] += x[i] (FP64).
 void axpy1(const double* x, double* y, int64_t n, hipStream_t s);
-// Kt[r][i*o + j] = gT[r][i] * rT[r][j] (* ij_scale[i*o + j] when given), converted to `kt`.
+// Kt[r][i*o + j] = gT[r][i] * rT[r][j] (* ij_scale[i*o + j], * r_scale[r] when given),
+// converted to `kt`.
 void khatri_rao_t(const double* gT, const double* rT, int64_t o, int64_t R, void* Kt, DType kt,
-                  hipStream_t s, const float* ij_scale = nullptr);
+                  hipStream_t s, const float* ij_scale = nullptr, const double* r_scale = nullptr);
+// x[i][j][a][b] <- (x[i][j][a][b] + x[j][i][b][a]) / 2 in place (o x o x v x v, FP64).
+void symmetrize_pairs(double* x, int64_t o, int64_t v, hipStream_t s);
 // OCP e4m3 copies with power-of-two scales:
 // scale[r] = least 2^e (e in [-126, 127]) with max_k |x[r][k]| <= 448 * 2^e, rows x len row-major;
 void e4m3_row_scales(const double* x, int64_t rows, int64_t len, float* scale, hipStream_t s);

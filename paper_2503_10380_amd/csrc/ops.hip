@@ -90,7 +90,8 @@ __global__ void axpy1_kernel(const double* __restrict__ x, double* y, int64_t n)
 }
 
 __global__ void kr_kernel(const double* __restrict__ gT, const double* __restrict__ rT, int64_t o,
-                          int64_t R, void* Kt, DType kt, const float* __restrict__ ij_scale) {
+                          int64_t R, void* Kt, DType kt, const float* __restrict__ ij_scale,
+                          const double* __restrict__ r_scale) {
   const int64_t total = R * o * o;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -98,7 +99,24 @@ __global__ void kr_kernel(const double* __restrict__ gT, const double* __restric
     const int64_t i = ij / o, j = ij % o;
     double k = gT[r * o + i] * rT[r * o + j];
     if (ij_scale) k *= (double)ij_scale[ij];
+    if (r_scale) k *= r_scale[r];
     put_dt(Kt, kt, e, k);
+  }
+}
+
+// x[i][j][a][b] <- (x[i][j][a][b] + x[j][i][b][a]) / 2, each pair once.
+__global__ void symmetrize_pairs_kernel(double* x, int64_t o, int64_t v) {
+  const int64_t n = o * o * v * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ij = e / (v * v), ab = e % (v * v);
+    const int64_t i = ij / o, j = ij % o, a = ab / v, b = ab % v;
+    const int64_t f = (j * o + i) * v * v + b * v + a;
+    if (e < f) {
+      const double m = 0.5 * (x[e] + x[f]);
+      x[e] = m;
+      x[f] = m;
+    }
   }
 }
 
@@ -438,9 +456,9 @@ void axpy1(const double* x, double* y, int64_t n, hipStream_t s) {
 }
 
 void khatri_rao_t(const double* gT, const double* rT, int64_t o, int64_t R, void* Kt, DType kt,
-                  hipStream_t s, const float* ij_scale) {
+                  hipStream_t s, const float* ij_scale, const double* r_scale) {
   hipLaunchKernelGGL(kr_kernel, dim3(blocks_for(R * o * o)), dim3(TPB), 0, s, gT, rT, o, R, Kt, kt,
-                     ij_scale);
+                     ij_scale, r_scale);
   CPPPL_LAUNCH_CHECK("khatri_rao");
 }
 
@@ -464,6 +482,13 @@ void expand_scales(const float* scale, float* out, int64_t nx, int64_t v, hipStr
   if (nx * v <= 0) return;
   hipLaunchKernelGGL(expand_scales_kernel, dim3(blocks_for(nx * v)), dim3(TPB), 0, s, scale, out, nx, v);
   CPPPL_LAUNCH_CHECK("expand_scales");
+}
+
+void symmetrize_pairs(double* x, int64_t o, int64_t v, hipStream_t s) {
+  const int64_t n = o * o * v * v;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(symmetrize_pairs_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, x, o, v);
+  CPPPL_LAUNCH_CHECK("symmetrize_pairs");
 }
 
 void dress_tau(const double* t2, const double* t1, double* tau, int64_t o, int64_t v, hipStream_t s) {
