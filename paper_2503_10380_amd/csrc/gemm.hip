@@ -9,13 +9,12 @@
 //  * v_mfma_f64_16x16x4f64: lane l needs A(l%16, l/16) and B(l/16, l%16), one
 //    double each, so tiles are kept k-major (As[k][m], Bs[k][n]); its result
 //    element (i, j) is register i/4 of lane j + 16 (i%4);
-//  * v_mfma_f32_16x16x32_bf16: lane l needs 8 consecutive k of row l%16, so
-//    tiles are kept m-major / n-major with 8 bf16 of padding per row
-//    (As[m][k], Bs[n][k]; the padded 144-byte rows make the 16-byte reads of
-//    16 lanes fall on 64 distinct banks); its result element (i, j) is
-//    register i%4 of lane j + 16 (i/4).
-// An operand whose contiguous index is not the one the LDS layout wants is
-// transposed on its way from registers into LDS; global reads stay coalesced.
+//  * v_mfma_f32_16x16x32_bf16: lane l needs 8 consecutive k of row l%16; a
+//    k-contiguous operand is kept [row][k] with XOR-swizzled 16-byte chunks
+//    (see BfTile), a row-contiguous one [k][row] as loaded and read with a
+//    transposing LDS load; its result element (i, j) is register i%4 of lane
+//    j + 16 (i/4).
+// Global reads stay coalesced in both cases.
 // Work-group ids are remapped so that each XCD owns a contiguous range of
 // tiles, and inside a batch the tile dimension with fewer tiles runs fastest,
 // so the larger operand is streamed from HBM about once.
@@ -89,7 +88,7 @@ __device__ __forceinline__ void store_out(const KArgs& a, const Coords& tc, int6
 
 // ------------------------------------------------------------------ FP64 ----
 template <int BM, int BN, bool AK, bool BKC>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const KArgs a) {
+__global__ __launch_bounds__(256, BM > 64 ? 2 : 1) void gemm_f64_kernel(const KArgs a) {
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
@@ -216,25 +215,27 @@ __device__ __forceinline__ s4_t lds_read_tr(const bf16_t* p) {
 }
 
 // One operand tile (ROWS x BBK) of a BF16 GEMM: global -> registers -> LDS.
-// KC: the operand's unit stride is along k; the tile is kept [row][k] and a
-// fragment is one 16-byte read.  With BBK = 32 the rows are unpadded (64 bytes)
-// and the 16-byte chunk index is XOR-ed with bits 2-3 of the row, so both the
-// stores (4 rows x 4 chunks per 16 lanes) and the fragment reads (16 rows, one
-// chunk) hit distinct banks; with BBK = 64 rows are padded to 144 bytes.
+// KC: the operand's unit stride is along k; the tile is kept [row][k] with
+// unpadded rows and a fragment is one 16-byte read.  The 16-byte chunk index is
+// XOR-ed with (row >> 1) & 3 (BBK = 32, 64-byte rows) or row & 7 (BBK = 64,
+// 128-byte rows): measured on gfx950 with the LDS bank-conflict counter, this
+// makes both the tile stores (4 or 8 lanes per row) and the fragment reads
+// (16 rows, one chunk) conflict-free, where a swizzle by row bits 2-3, plain
+// rows or 144-byte padded rows leave the fragment reads two-way conflicted.
 // Otherwise the unit stride is along the row index; the tile is kept [k][row]
 // (16-byte stores straight from the coalesced loads, rows padded to 288 bytes so
 // the 16 rows read by one transposing instruction fall on disjoint bank groups)
 // and a fragment is two transposing reads.
 template <int ROWS, bool KC, int BBK>
 struct BfTile {
-  static constexpr bool SWZ = BBK == 32;              // XOR-swizzled [row][k] layout
-  static constexpr int BLDK = SWZ ? BBK : BBK + 8;      // row pitch of the [row][k] layout
+  static constexpr int BLDK = BBK;                      // row pitch of the [row][k] layout
   static constexpr int C = ROWS * BBK / 8 / 256;
   static constexpr int LDT = ROWS + 16;                 // row pitch of the [k][row] layout
   static constexpr int SIZE = KC ? ROWS * BLDK : BBK * LDT;  // bf16 elements per buffer
   // element offset of (row, kk) in the [row][k] layout, kk a multiple of 8
   __device__ __forceinline__ static int kc_off(int row, int kk) {
-    return SWZ ? row * BLDK + (((kk >> 3) ^ ((row >> 2) & 3)) << 3) : row * BLDK + kk;
+    const int swz = BBK == 32 ? (row >> 1) & 3 : row & 7;
+    return row * BLDK + (((kk >> 3) ^ swz) << 3);
   }
   __device__ __forceinline__ static void load(uint4 (&r)[C], const bf16_t* X, int64_t s_row,
                                               int64_t s_k, int64_t row0, int64_t nrows, int64_t k0,
@@ -347,7 +348,7 @@ template <> __device__ __forceinline__ bf16_t to_out<bf16_t>(float v) { return f
 template <> __device__ __forceinline__ double to_out<double>(float v) { return (double)v; }
 
 template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT, bool B8 = false>
-__global__ __launch_bounds__(256, BBK == BBK_LONG ? 2 : ((AK && BKC && sizeof(OutT) <= 4) ? 4 : 3))
+__global__ __launch_bounds__(256, BBK == BBK_LONG ? 2 : ((AK && BKC && !B8 && sizeof(OutT) <= 4) ? 4 : 3))
 void gemm_bf16_kernel(const KArgs a) {
   static_assert(!B8 || BKC, "an e4m3 B operand must be k-contiguous");
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -621,24 +622,38 @@ int choose_splits(int64_t tiles, int64_t K, int64_t target_blocks, int64_t min_k
   return (int)std::max<int64_t>(1, s);
 }
 
-int64_t gemm_tiles_f64(int64_t M, int64_t N) { return ((M + 63) / 64) * ((N + 63) / 64); }
+// Output tile rows of the FP64 kernel (64 columns): 128 when the problem is
+// tall enough (each wave then owns 64 x 32 and issues twice the matrix-core
+// work per staged slice), else 64.
+static int f64_tile_m(int64_t M, int64_t N) { return (M >= 128 && N >= 64) ? 128 : 64; }
+int64_t gemm_tiles_f64(int64_t M, int64_t N) {
+  const int64_t t = f64_tile_m(M, N);
+  return ((M + t - 1) / t) * ((N + 63) / 64);
+}
 int64_t gemm_tiles_bf16(int64_t M, int64_t N) { return ((M + 127) / 128) * ((N + 127) / 128); }
+
+template <int T>
+static void launch_f64(const KArgs& a, bool ak, bool bk, dim3 grid, hipStream_t s) {
+  dim3 block(256);
+  if (ak && bk) hipLaunchKernelGGL((gemm_f64_kernel<T, 64, true, true>), grid, block, 0, s, a);
+  else if (ak && !bk) hipLaunchKernelGGL((gemm_f64_kernel<T, 64, true, false>), grid, block, 0, s, a);
+  else if (!ak && bk) hipLaunchKernelGGL((gemm_f64_kernel<T, 64, false, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gemm_f64_kernel<T, 64, false, false>), grid, block, 0, s, a);
+}
 
 void gemm_f64(const Gemm& g, hipStream_t s) {
   check_operand_strides(g);
   if (g.ctype != DType::F64) throw std::invalid_argument("gemm_f64: output must be FP64");
-  constexpr int BM = 64, BN = 64;
-  KArgs a = make_args(g, BM, BN, 16);
+  const int T = f64_tile_m(g.M, g.N);
+  KArgs a = make_args(g, T, 64, 16);
   if (a.splits > 1 && !a.partial) throw std::invalid_argument("gemm_f64: split-K needs a partial buffer");
   const int64_t blocks = a.tiles_m * a.tiles_n * a.batch * a.splits;
   if (blocks == 0) return;
   if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_f64: grid too large");
   const bool ak = g.sak == 1, bk = g.sbk == 1;
-  dim3 grid((unsigned)blocks), block(256);
-  if (ak && bk) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, true>), grid, block, 0, s, a);
-  else if (ak && !bk) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, true, false>), grid, block, 0, s, a);
-  else if (!ak && bk) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, false, false>), grid, block, 0, s, a);
+  dim3 grid((unsigned)blocks);
+  if (T == 128) launch_f64<128>(a, ak, bk, grid, s);
+  else launch_f64<64>(a, ak, bk, grid, s);
   CPPPL_LAUNCH_CHECK("gemm_f64");
   if (a.splits > 1) launch_reduce<double, double>(a, s);
 }
