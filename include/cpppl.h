@@ -165,6 +165,14 @@ CPPPL_API cpppl_status cpppl_norm_r2(cpppl_ctx* ctx, double* norm_r2, double* en
 CPPPL_API cpppl_status cpppl_set_factors(cpppl_ctx* ctx, const double* fi, const double* fj,
                                          const double* fa, const double* fb, const double* lam,
                                          int on_device);
+/* The paper's random guess (Section "An improved initial guess strategy":
+ * factors drawn uniformly from [-1, 1]) on the device: element (row, r) of factor m, in the
+ * API order (i, j, a, b) = (gamma, rho, alpha, beta), is
+ * u(offset_m + row * R + r) with offset_m the element count of the factors
+ * before m, where u(c) = 2^-52 (z >> 11) - 1 and z is output number c + 1 of
+ * SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) seeded with `seed`; lambda = 1.
+ * Reproducible from the seed alone; synchronises. */
+CPPPL_API cpppl_status cpppl_init_random(cpppl_ctx* ctx, uint64_t seed);
 /* Any output pointer may be NULL. */
 CPPPL_API cpppl_status cpppl_get_factors(cpppl_ctx* ctx, double* fi, double* fj, double* fa,
                                          double* fb, double* lam, int on_device);

@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "cpppl_norm_r2": (st, [_P, _D, _D]),
         "cpppl_set_factors": (st, [_P, _P, _P, _P, _P, _P, C.c_int]),
         "cpppl_get_factors": (st, [_P, _P, _P, _P, _P, _P, C.c_int]),
+        "cpppl_init_random": (st, [_P, C.c_uint64]),
         "cpppl_als": (st, [_P, C.POINTER(AlsOpts), C.POINTER(AlsReport)]),
         "cpppl_mttkrp": (st, [_P, C.c_int, C.c_int, _P, C.c_int]),
         "cpppl_fit": (st, [_P, _D, _D, _D]),
@@ -245,6 +246,10 @@ class Context:
         return n2.value, e.value
 
     # ------------------------------------------------------------------ factors
+    def init_random(self, seed):
+        """Factors uniform in [-1, 1) from the library's counter-based generator, lambda = 1."""
+        self._call("cpppl_init_random", C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF))
+
     def set_factors(self, fi, fj, fa, fb, lam=None):
         keep = []
         shapes = [(self.o, self.rank), (self.o, self.rank), (self.v, self.rank), (self.v, self.rank)]

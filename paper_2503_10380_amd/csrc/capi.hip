@@ -1155,6 +1155,24 @@ CPPPL_API cpppl_status cpppl_set_factors(cpppl_ctx* c, const double* fi, const d
   API_CATCH(c)
 }
 
+CPPPL_API cpppl_status cpppl_init_random(cpppl_ctx* c, uint64_t seed) {
+  API_TRY(c)
+  need_ws(c);
+  const Plan& p = c->plan;
+  const int64_t R = c->d.rank;
+  uint64_t offset = 0;
+  for (int m = 0; m < 4; ++m) {  // API order (i, j, a, b), element (row, r) is draw offset + row R + r
+    const int64_t n = nmode(c->d, m);
+    random_factor(c->at<double>(p.FT[m]), n, R, seed, offset, c->stream);
+    offset += (uint64_t)(n * R);
+  }
+  fill_doubles(c->at<double>(p.lam), R, 1.0, c->stream);
+  init_after_factors(c);
+  c->ws_valid = false;
+  sync(c);
+  API_CATCH(c)
+}
+
 CPPPL_API cpppl_status cpppl_get_factors(cpppl_ctx* c, double* fi, double* fj, double* fa,
                                          double* fb, double* lam, int on_device) {
   API_TRY(c)

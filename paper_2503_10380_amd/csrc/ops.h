@@ -75,6 +75,11 @@ void set_scalar(double* p, double v, hipStream_t s);
 void finish_eta(double* sc_eta, hipStream_t s);
 // Count non-finite entries of x into *flag (flag must be zeroed by the caller).
 void nonfinite_check(const double* x, int64_t n, int* flag, hipStream_t s);
+// FT[r][i] (R x n) = uniform [-1, 1) number offset + i R + r of a counter-based
+// SplitMix64 stream seeded with `seed` (Steele, Lea and Flood, OOPSLA 2014).
+void random_factor(double* FT, int64_t n, int64_t R, uint64_t seed, uint64_t offset, hipStream_t s);
+// p[i] = v for i < n.
+void fill_doubles(double* p, int64_t n, double v, hipStream_t s);
 // Zero n ints / doubles with a kernel (graph-capture safe).
 void zero_ints(int* p, int64_t n, hipStream_t s);
 void zero_doubles(double* p, int64_t n, hipStream_t s);

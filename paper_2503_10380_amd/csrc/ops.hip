@@ -385,6 +385,31 @@ __global__ void zero_doubles_kernel(double* p, int64_t n) {
     p[i] = 0.0;
 }
 
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) used counter-based: output
+// number c + 1 of the generator seeded with `seed`, mapped to [-1, 1) exactly.
+__device__ inline double splitmix_uniform(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * 0x1p-52 - 1.0;
+}
+
+// FT[r][i] (R x n) = U[-1, 1) draw number offset + i R + r.
+__global__ void random_factor_kernel(double* FT, int64_t n, int64_t R, uint64_t seed, uint64_t offset) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * R;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n, i = e % n;
+    FT[e] = splitmix_uniform(seed, offset + (uint64_t)(i * R + r));
+  }
+}
+
+__global__ void fill_doubles_kernel(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 __global__ void hadamard_scale_cols_kernel(const double* X0, const double* X1, const double* X2,
                                            const double* lamP, double* C, int64_t R, int64_t P) {
   const int64_t total = R * P;
@@ -597,6 +622,18 @@ void zero_doubles(double* p, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(zero_doubles_kernel, dim3(blocks_for(n, 4096)), dim3(TPB), 0, s, p, n);
   CPPPL_LAUNCH_CHECK("zero_doubles");
+}
+
+void random_factor(double* FT, int64_t n, int64_t R, uint64_t seed, uint64_t offset, hipStream_t s) {
+  if (n * R <= 0) return;
+  hipLaunchKernelGGL(random_factor_kernel, dim3(blocks_for(n * R)), dim3(TPB), 0, s, FT, n, R, seed, offset);
+  CPPPL_LAUNCH_CHECK("random_factor");
+}
+
+void fill_doubles(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_doubles_kernel, dim3(blocks_for(n, 4096)), dim3(TPB), 0, s, p, n, v);
+  CPPPL_LAUNCH_CHECK("fill_doubles");
 }
 
 void hadamard_scale_cols(const double* X0, const double* X1, const double* X2, const double* lamP,

@@ -298,3 +298,25 @@ def test_eta_stop_rule(lib):
     r = ctx.als(40, stop_rule=2, tol=tol)
     assert r["sweeps"] == want + 1
     np.testing.assert_allclose(r["eta_hist"], eta[:want + 1], rtol=1e-12, atol=0)
+
+
+def test_init_random_matches_oracle_generator(lib):
+    """cpppl_init_random draws the paper's U[-1, 1] guess from counter-based
+    SplitMix64: bitwise the oracle's draws, lambda = 1, and ALS from it follows
+    the oracle's trajectory."""
+    from oracle import rng
+    cfg = SMALL["ragged_tiles"]
+    _say("init_random")
+    inp, r = _problem(cfg)
+    ctx = _ctx(lib, cfg, inp)
+    for seed in (0, 12345, 2 ** 63 + 5):
+        ctx.init_random(seed)
+        got = ctx.get_factors()
+        want = rng.random_guess(cfg.o, cfg.v, cfg.rank, seed)
+        for g, w in zip(got[:4], want):
+            np.testing.assert_array_equal(g, w)
+        np.testing.assert_array_equal(got[4], np.ones(cfg.rank))
+    rep = ctx.als(5)
+    _, _, hist = oracle.cp_als(r, want, 5, norm_r2=float(np.sum(r * r)))
+    np.testing.assert_allclose(rep["fit_hist"], hist["fit"], rtol=0, atol=1e-9)
+    ctx.close()
