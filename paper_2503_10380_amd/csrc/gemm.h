@@ -48,6 +48,7 @@ void gemm_bf16(const Gemm& g, hipStream_t s);
 int choose_splits(int64_t tiles, int64_t K, int64_t target_blocks, int64_t min_k, int max_splits);
 
 int64_t gemm_tiles_f64(int64_t M, int64_t N);
+// 128 x 128 output tiles of an M x N result (the tiles of every split-K gemm_bf16).
 int64_t gemm_tiles_bf16(int64_t M, int64_t N);
 
 }  // namespace cpppl

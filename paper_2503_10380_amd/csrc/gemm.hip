@@ -226,10 +226,11 @@ __device__ __forceinline__ s4_t lds_read_tr(const bf16_t* p) {
 // (16-byte stores straight from the coalesced loads, rows padded to 288 bytes so
 // the 16 rows read by one transposing instruction fall on disjoint bank groups)
 // and a fragment is two transposing reads.
-template <int ROWS, bool KC, int BBK>
+template <int ROWS, bool KC, int BBK, int NT = 256>
 struct BfTile {
   static constexpr int BLDK = BBK;                      // row pitch of the [row][k] layout
-  static constexpr int C = ROWS * BBK / 8 / 256;
+  static_assert(ROWS * BBK % (8 * NT) == 0, "tile chunks must divide evenly over the lanes");
+  static constexpr int C = ROWS * BBK / 8 / NT;
   static constexpr int LDT = ROWS + 16;                 // row pitch of the [k][row] layout
   static constexpr int SIZE = KC ? ROWS * BLDK : BBK * LDT;  // bf16 elements per buffer
   // element offset of (row, kk) in the [row][k] layout, kk a multiple of 8
@@ -242,7 +243,7 @@ struct BfTile {
                                               int64_t kend, bool vec, int tid) {
 #pragma unroll
     for (int e = 0; e < C; ++e) {
-      const int c = tid + e * 256;
+      const int c = tid + e * NT;
       if (KC) {
         const int row = c / (BBK / 8), kk = (c % (BBK / 8)) * 8;
         const int64_t g = row0 + row, gk = k0 + kk;
@@ -261,7 +262,7 @@ struct BfTile {
   __device__ __forceinline__ static void store(const uint4 (&r)[C], bf16_t* S, int tid) {
 #pragma unroll
     for (int e = 0; e < C; ++e) {
-      const int c = tid + e * 256;
+      const int c = tid + e * NT;
       if (KC) {
         const int row = c / (BBK / 8), kk = (c % (BBK / 8)) * 8;
         *(uint4*)&S[kc_off(row, kk)] = r[e];
@@ -347,21 +348,28 @@ template <> __device__ __forceinline__ float to_out<float>(float v) { return v; 
 template <> __device__ __forceinline__ bf16_t to_out<bf16_t>(float v) { return f32_to_bf16(v); }
 template <> __device__ __forceinline__ double to_out<double>(float v) { return (double)v; }
 
-template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT, bool B8 = false>
-__global__ __launch_bounds__(256, BBK == BBK_LONG ? 2 : ((AK && BKC && !B8 && sizeof(OutT) <= 4) ? 4 : 3))
+// WGM wave rows by 2 wave columns: 4 waves (128 x 128 tiles, 3 or 4 work-groups
+// per CU) or 8 waves (256 x 128 tiles, two per CU: each operand element staged
+// in LDS then feeds 256 or 128 products instead of 128, a quarter less LDS
+// writing and L2 reading per flop at the same 64 x 64 tile per wave).
+template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT, bool B8 = false, int WGM = 2>
+__global__ __launch_bounds__(128 * WGM, WGM == 4 ? 4 : (BBK == BBK_LONG ? 2 : ((AK && BKC && !B8 && sizeof(OutT) <= 4) ? 4 : 3)))
 void gemm_bf16_kernel(const KArgs a) {
   static_assert(!B8 || BKC, "an e4m3 B operand must be k-contiguous");
-  constexpr int WM = BM / 2, WN = BN / 2;
+  static_assert(WGM == 2 || (WGM == 4 && BBK == BBK_SHORT && AK && BKC && !B8),
+                "8-wave tiles: k-contiguous BF16 operands, short slices");
+  constexpr int NT = 128 * WGM;
+  constexpr int WM = BM / WGM, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  using TA = BfTile<BM, AK, BBK>;
-  using TB = BfTile<BN, BKC, BBK>;
+  using TA = BfTile<BM, AK, BBK, NT>;
+  using TB = BfTile<BN, BKC, BBK, NT>;
   constexpr int AS = TA::SIZE, BS = TB::SIZE;  // bf16 elements per buffer
-  // staged epilogue: 2-byte results in one pass, 4-byte results (FP32 output
-  // or split-K partials) in two passes of BM / 2 rows
+  // staged epilogue: 2-byte results in passes of 128 rows (two wave rows),
+  // 4-byte results (FP32 output or split-K partials) in passes of one wave row
   constexpr bool STAGE = sizeof(OutT) <= 4;
   constexpr int LDC2 = BN + 8, LDC4 = BN + 4;
   constexpr int SMEM_AB = 2 * (AS + BS) * 2;
-  constexpr int SMEM_C2 = BM * LDC2 * 2, SMEM_C4 = (BM / 2) * LDC4 * 4;
+  constexpr int SMEM_C2 = 2 * WM * LDC2 * 2, SMEM_C4 = WM * LDC4 * 4;
   constexpr int SMEM_C = SMEM_C2 > SMEM_C4 ? SMEM_C2 : SMEM_C4;
   constexpr int SMEM = SMEM_AB > SMEM_C ? SMEM_AB : SMEM_C;
   __shared__ __attribute__((aligned(16))) char smem[SMEM];
@@ -478,30 +486,36 @@ void gemm_bf16_kernel(const KArgs a) {
     if (!part && sizeof(OutT) == 2) {
       bf16_t* Cs = (bf16_t*)smem;
       const float alpha = (float)a.alpha;
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          const int lm = wm * WM + i * 16 + lr;
-          const int ln = wn * WN + j * 16 + lc;
-          const uint32_t w0 = (uint32_t)f32_to_bf16(alpha * acc[i][j][0]) |
-                              ((uint32_t)f32_to_bf16(alpha * acc[i][j][1]) << 16);
-          const uint32_t w1 = (uint32_t)f32_to_bf16(alpha * acc[i][j][2]) |
-                              ((uint32_t)f32_to_bf16(alpha * acc[i][j][3]) << 16);
-          *(uint2*)&Cs[lm * LDC2 + ln] = make_uint2(w0, w1);
-        }
-      __syncthreads();
-      constexpr int EPC = 8, CPR = BN / EPC;
+      constexpr int EPC = 8, CPR = BN / EPC, PROWS = 2 * WM;
       bf16_t* dst = (bf16_t*)a.C + tc.b * a.scb;
-      for (int c = tid; c < BM * CPR; c += 256) {
-        const int row = c / CPR, col = (c % CPR) * EPC;
-        const int64_t gm = m0 + row, gn = n0 + col;
-        if (gm >= a.M) continue;
-        if (a.cvec_ok && gn + EPC <= a.N) {
-          *(uint4*)(dst + gm * a.scm + gn) = *(const uint4*)(Cs + row * LDC2 + col);
-        } else {
-          for (int q = 0; q < EPC; ++q)
-            if (gn + q < a.N) dst[gm * a.scm + gn + q] = Cs[row * LDC2 + col + q];
+#pragma unroll
+      for (int pass = 0; pass < WGM / 2; ++pass) {
+        if (pass > 0) __syncthreads();
+        if ((wm >> 1) == pass) {
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              const int lm = (wm & 1) * WM + i * 16 + lr;
+              const int ln = wn * WN + j * 16 + lc;
+              const uint32_t w0 = (uint32_t)f32_to_bf16(alpha * acc[i][j][0]) |
+                                  ((uint32_t)f32_to_bf16(alpha * acc[i][j][1]) << 16);
+              const uint32_t w1 = (uint32_t)f32_to_bf16(alpha * acc[i][j][2]) |
+                                  ((uint32_t)f32_to_bf16(alpha * acc[i][j][3]) << 16);
+              *(uint2*)&Cs[lm * LDC2 + ln] = make_uint2(w0, w1);
+            }
+        }
+        __syncthreads();
+        for (int c = tid; c < PROWS * CPR; c += NT) {
+          const int row = c / CPR, col = (c % CPR) * EPC;
+          const int64_t gm = m0 + pass * PROWS + row, gn = n0 + col;
+          if (gm >= a.M) continue;
+          if (a.cvec_ok && gn + EPC <= a.N) {
+            *(uint4*)(dst + gm * a.scm + gn) = *(const uint4*)(Cs + row * LDC2 + col);
+          } else {
+            for (int q = 0; q < EPC; ++q)
+              if (gn + q < a.N) dst[gm * a.scm + gn + q] = Cs[row * LDC2 + col + q];
+          }
         }
       }
     } else {
@@ -513,7 +527,7 @@ void gemm_bf16_kernel(const KArgs a) {
       const int64_t ldd = part ? a.N : a.scm;
       constexpr int EPC = 4, CPR = BN / EPC;
 #pragma unroll
-      for (int pass = 0; pass < 2; ++pass) {
+      for (int pass = 0; pass < WGM; ++pass) {
         if (wm == pass) {
 #pragma unroll
           for (int i = 0; i < TM; ++i)
@@ -525,9 +539,9 @@ void gemm_bf16_kernel(const KArgs a) {
             }
         }
         __syncthreads();
-        for (int c = tid; c < (BM / 2) * CPR; c += 256) {
+        for (int c = tid; c < WM * CPR; c += NT) {
           const int row = c / CPR, col = (c % CPR) * EPC;
-          const int64_t gm = m0 + pass * (BM / 2) + row, gn = n0 + col;
+          const int64_t gm = m0 + pass * WM + row, gn = n0 + col;
           if (gm >= a.M) continue;
           if (a.cvec_ok && gn + EPC <= a.N) {
             *(uint4*)(dst + gm * ldd + gn) = *(const uint4*)(Cs + row * LDC4 + col);
@@ -630,6 +644,18 @@ int64_t gemm_tiles_f64(int64_t M, int64_t N) {
   const int64_t t = f64_tile_m(M, N);
   return ((M + t - 1) / t) * ((N + 63) / 64);
 }
+// BF16 output tile rows: 256 (eight waves) for an unsplit product of two
+// k-contiguous BF16 operands with K >= 1024, when M is a multiple of 256 of at
+// least 512 or is at least 2048 (a ragged last tile row then wastes little);
+// else 128.  Measured on MI355X, the 256-row tiles gain 2-11 % on such long-K
+// products (the Khatri-Rao x t2 step) but lose 2-6 % on short K (v) and up to
+// a third on split-K products, which keep 128 x 128 tiles with K slices of 64.
+// (The transposing loads of row-contiguous operands would also need more
+// registers than four waves per SIMD leave.)
+static int bf16_tile_m(const Gemm& g) {
+  const bool ok = g.sak == 1 && g.sbk == 1 && !g.b_fp8 && g.splits <= 1 && g.K >= 1024;
+  return (ok && g.M >= 512 && (g.M % 256 == 0 || g.M >= 2048)) ? 256 : 128;
+}
 int64_t gemm_tiles_bf16(int64_t M, int64_t N) { return ((M + 127) / 128) * ((N + 127) / 128); }
 
 template <int T>
@@ -658,15 +684,16 @@ void gemm_f64(const Gemm& g, hipStream_t s) {
   if (a.splits > 1) launch_reduce<double, double>(a, s);
 }
 
-template <int BK, bool AK, bool BKC, bool B8 = false>
+template <int BK, bool AK, bool BKC, bool B8 = false, int WGM = 2>
 static void launch_bf16(const KArgs& a, DType ct, dim3 grid, hipStream_t s) {
-  constexpr int BM = 128, BN = 128;
+  constexpr int BM = 64 * WGM, BN = 128;
+  const dim3 block(128 * WGM);
   if (ct == DType::F32 || a.splits > 1)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, float, B8>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, float, B8, WGM>), grid, block, 0, s, a);
   else if (ct == DType::BF16)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, bf16_t, B8>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, bf16_t, B8, WGM>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, double, B8>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, double, B8, WGM>), grid, block, 0, s, a);
 }
 
 template <int BK>
@@ -681,12 +708,13 @@ static void launch_bf16_layout(const KArgs& a, bool ak, bool bk, DType ct, dim3 
 void gemm_bf16(const Gemm& g, hipStream_t s) {
   check_operand_strides(g);
   if (g.beta != 0.0 && g.splits <= 1) throw std::invalid_argument("gemm_bf16: beta must be 0");
-  constexpr int BM = 128, BN = 128;
+  const bool ak = g.sak == 1, bk = g.sbk == 1;
+  const int BM = bf16_tile_m(g), BN = 128;
   const int64_t kper = (g.K + std::max(1, g.splits) - 1) / std::max(1, g.splits);
-  const int bk_slice = kper >= BBK_LONG_MIN_K ? BBK_LONG : BBK_SHORT;
+  // 256-row tiles always walk K in short slices (their LDS stages are twice as large)
+  const int bk_slice = (BM == 128 && kper >= BBK_LONG_MIN_K) ? BBK_LONG : BBK_SHORT;
   KArgs a = make_args(g, BM, BN, bk_slice);
   if (a.splits > 1 && !a.partial) throw std::invalid_argument("gemm_bf16: split-K needs a partial buffer");
-  const bool ak = g.sak == 1, bk = g.sbk == 1;
   if (g.b_fp8) {
     if (!bk) throw std::invalid_argument("gemm_bf16: an e4m3 B must be k-contiguous");
     if (g.bscale_mode < 0 || g.bscale_mode > 2) throw std::invalid_argument("gemm_bf16: bad bscale_mode");
@@ -716,6 +744,8 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
       if (ak) launch_bf16<BBK_SHORT, true, true, true>(a, g.ctype, grid, s);
       else launch_bf16<BBK_SHORT, false, true, true>(a, g.ctype, grid, s);
     }
+  } else if (BM == 256) {
+    launch_bf16<BBK_SHORT, true, true, false, 4>(a, g.ctype, grid, s);
   } else if (bk_slice == BBK_LONG) {
     launch_bf16_layout<BBK_LONG>(a, ak, bk, g.ctype, grid, s);
   } else {

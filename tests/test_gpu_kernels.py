@@ -60,6 +60,8 @@ CASES = [
     (5, 3, 1, 3, 1),
     (130, 200, 4104, 1, 1),     # BF16: K slices of 64, odd slice count
     (257, 129, 9000, 2, 2),     # BF16: K slices of 64 per split, ragged tail
+    (512, 130, 1100, 1, 1),     # BF16 k-contiguous: 256-row tiles, ragged K tail
+    (2100, 70, 1040, 2, 1),     # BF16 k-contiguous: 256-row tiles, ragged last tile row
 ]
 
 
@@ -89,6 +91,40 @@ def test_gemm_layouts(env, dtype, ak, bk, case):
     err = np.abs(got - want).max() / max(1e-300, np.abs(want).max())
     tol = 1e-13 if dtype == "f64" else 5e-5
     assert err <= tol, err
+
+
+STAGED = [
+    # (M, N, K, batch, splits), both operands k-contiguous
+    (512, 200, 1024, 2, 1),     # 256-row tiles
+    (768, 256, 1100, 1, 1),     # 256-row tiles, ragged K tail
+    (2100, 130, 1030, 1, 1),    # 256-row tiles, ragged last tile row
+    (512, 200, 96, 2, 1),       # 128-row tiles, short K
+    (1024, 64, 3000, 1, 4),     # 128-row tiles, split-K
+]
+
+
+@pytest.mark.parametrize("out", ["f32", "bf16"])
+@pytest.mark.parametrize("case", STAGED)
+def test_gemm_bf16_outputs(env, out, case):
+    """FP32 and BF16 results (the LDS-staged epilogue), split-K included."""
+    L, torch = env
+    M, N, K, batch, splits = case
+    _say(f"gemm bf16 -> {out} case={case}")
+    rng = np.random.default_rng(hash((M, N, K, batch, out)) % 2 ** 32)
+    a, ta, sam, sak, sab = _operand(torch, rng, batch, M, K, 1, "bf16")
+    b, tb, sbk, sbn, sbb = _operand(torch, rng, batch, K, N, 0, "bf16")
+    tdt = torch.float32 if out == "f32" else torch.bfloat16
+    tc = torch.full((batch * M * N,), 7.0, dtype=tdt, device="cuda")
+    part = torch.zeros(max(1, splits * batch * M * N), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    st = L.cpppl_test_gemm(1, M, N, K, batch, ta.data_ptr(), sam, sak, sab, tb.data_ptr(), sbk,
+                           sbn, sbb, tc.data_ptr(), N, M * N, 1 if out == "f32" else 2, 0.75, 0.0,
+                           splits, part.data_ptr(), stream)
+    assert st == 0
+    want = 0.75 * np.einsum("bmk,bkn->bmn", a, b)
+    got = tc.to(torch.float64).cpu().numpy().reshape(batch, M, N)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err <= (5e-5 if out == "f32" else 8e-3), err
 
 
 @pytest.mark.parametrize("R,n", [(1, 3), (17, 5), (64, 64), (65, 7), (300, 130), (1024, 256),
