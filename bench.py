@@ -85,16 +85,21 @@ def traffic_for(kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
-# BF16 GEMM launches of one ALS sweep in issue order (main stream).
+# BF16 products of one ALS sweep in issue order (main stream).  While a
+# side-stream inverse is pending the library cuts each unsplit product into
+# four launches (split-K products stay whole), so a class call is LAUNCHES[cls]
+# consecutive gemm_bf16_kernel dispatches.
 SWEEP_GEMMS = ["kr_t2", "z", "m", "y", "z", "m", "y", "g", "h"]
+LAUNCHES = {"kr_t2": 4, "y": 4, "z": 4, "g": 4, "m": 1, "h": 1}
 
 
 def digest_counters(fetch_csv, write_csv, steps, calib_mib, out_path):
     """HBM traffic per MTTKRP kernel class from two rocprofv3 --pmc runs
     (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
     `bench.py --steps S --warmup W --no-cpu --no-compare --copy-calibration MIB`.
-    The last 9 S BF16 GEMM dispatches are the timed sweeps, labelled by the
-    fixed issue order; a split-K reduction is charged to the GEMM before it.
+    The last S sweeps' BF16 GEMM dispatches are the timed sweeps, labelled by
+    the fixed issue order (LAUNCHES[cls] dispatches per class call); a split-K
+    reduction is charged to the GEMM before it.
     Each counter is scaled by (known bytes / counted bytes) of the plain device
     copies of MIB MiB issued first."""
     import csv
@@ -115,19 +120,26 @@ def digest_counters(fetch_csv, write_csv, steps, calib_mib, out_path):
         factor = known / (sum(big) / len(big))
         out["calibration"][name] = {"known_bytes": known, "counted_bytes": sum(big) / len(big),
                                     "factor": factor}
+        per_sweep = sum(LAUNCHES[c] for c in SWEEP_GEMMS)
         idx = [i for i, (k, _) in enumerate(d) if k.startswith("gemm_bf16_kernel")]
-        idx = idx[-9 * steps:]
-        for n, i in enumerate(idx):
-            cls = SWEEP_GEMMS[n % 9]
-            b = d[i][1]
-            if i + 1 < len(d) and d[i + 1][0].startswith("splitk_reduce_kernel"):
-                b += d[i + 1][1]
-            per.setdefault(cls, {}).setdefault(name, []).append(b * factor)
+        idx = idx[-per_sweep * steps:]
+        pos = 0
+        for _ in range(steps):
+            for cls in SWEEP_GEMMS:
+                b = 0.0
+                for i in idx[pos:pos + LAUNCHES[cls]]:
+                    b += d[i][1]
+                    if i + 1 < len(d) and d[i + 1][0].startswith("splitk_reduce_kernel"):
+                        b += d[i + 1][1]
+                pos += LAUNCHES[cls]
+                per.setdefault(cls, {}).setdefault(name, []).append(b * factor)
     for cls, v in per.items():
         f = sum(v["fetch"]) / len(v["fetch"])
         w = sum(v["write"]) / len(v["write"])
-        out["classes"][cls] = {"fetch_bytes_per_launch": f, "write_bytes_per_launch": w,
-                               "bytes_per_launch": f + w, "launches": len(v["fetch"])}
+        out["classes"][cls] = {"fetch_bytes_per_call": f, "write_bytes_per_call": w,
+                               "bytes_per_call": f + w, "calls": len(v["fetch"]),
+                               "launches_per_call": LAUNCHES[cls],
+                               "bytes_per_launch": (f + w) / LAUNCHES[cls]}
     with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
@@ -318,7 +330,7 @@ def precision_ablation(cp, torch, args):
             n = rep["n_class"][k]
             kms = rep["ms_class"][k]
             if n and kms > 0:
-                per_class[k] = {"ms_per_launch": kms / n, "tflops": flops[k] * n / (kms * 1e-3) / 1e12,
+                per_class[k] = {"ms_per_call": kms / n, "tflops": flops[k] * n / (kms * 1e-3) / 1e12,
                                 "gbs": nbytes[k] * n / (kms * 1e-3) / 1e9}
         mt_ms = sum(rep["ms_class"][k] for k in CLASSES)
         ctx.set_factors(*state)
@@ -558,8 +570,8 @@ def main():
     for k in CLASSES:
         n = rep["n_class"][k]
         ms = rep["ms_class"][k]
-        per_class[k] = {"launches": n, "ms_total": ms,
-                        "ms_per_launch": ms / n if n else None,
+        per_class[k] = {"calls": n, "launches_per_call": LAUNCHES[k], "ms_total": ms,
+                        "ms_per_call": ms / n if n else None,
                         "tflops": (flops[k] * n / (ms * 1e-3) / 1e12) if ms > 0 else None}
     per_class["solve"] = {"launches": rep["n_class"]["solve"], "ms_total": rep["ms_class"]["solve"]}
     per_class["fit"] = {"launches": rep["n_class"]["fit"], "ms_total": rep["ms_class"]["fit"]}
@@ -568,13 +580,16 @@ def main():
     mttkrp_ms = sum(rep["ms_class"][k] for k in CLASSES)
     mttkrp_tflops = sweep_flops(cfg) * args.steps / (mttkrp_ms * 1e-3) / 1e12
     dom = max(CLASSES, key=lambda k: rep["ms_class"][k])
-    d_launch_ms = rep["ms_class"][dom] / rep["n_class"][dom]
-    roofline = roofline_for(dom, flops[dom], nbytes[dom], d_launch_ms)
+    # per launch: a class call of the dominant kernel is LAUNCHES[dom] launches
+    nl = LAUNCHES[dom]
+    d_launch_ms = rep["ms_class"][dom] / (rep["n_class"][dom] * nl)
+    roofline = roofline_for(dom, flops[dom] / nl, nbytes[dom] / nl, d_launch_ms)
+    roofline["launches_per_call"] = nl
     for k in CLASSES:
-        if per_class[k]["ms_per_launch"]:
-            r = roofline_for(k, flops[k], nbytes[k], per_class[k]["ms_per_launch"])
+        if per_class[k]["ms_per_call"]:
+            r = roofline_for(k, flops[k], nbytes[k], per_class[k]["ms_per_call"])
             per_class[k].update({"bound": r["bound"], "frac": r["frac"],
-                                 "gbs": nbytes[k] / (per_class[k]["ms_per_launch"] * 1e-3) / 1e9})
+                                 "gbs": nbytes[k] / (per_class[k]["ms_per_call"] * 1e-3) / 1e9})
 
     out = {
         "metric": METRIC, "value": args.steps / wall, "unit": "sweeps/s", "n_gpus": 1,

@@ -86,7 +86,8 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   for (int m = 0; m < 4; ++m) {
     const size_t n = (size_t)nmode(d, m);
     p.FT[m] = add(n * R * 8);
-    p.FTprev[m] = add(n * R * 8);
+    p.FTprev[0][m] = add(n * R * 8);
+    p.FTprev[1][m] = add(n * R * 8);
     p.F16T[m] = lp ? add(n * R * 2) : 0;
     p.gram[m] = add((size_t)R * R * 8);
     p.cross[m] = add((size_t)R * R * 8);
@@ -95,7 +96,8 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
     p.wsD[m] = add(n * R * 8);
   }
   p.lam = add(R * 8);
-  p.lamprev = add(R * 8);
+  p.lamprev[0] = add(R * 8);
+  p.lamprev[1] = add(R * 8);
   p.lamp = add(R * 8);
   p.wsLam = add(R * 8);
   p.Cp = add((size_t)R * R * 8);
@@ -168,17 +170,46 @@ struct Span {
   int cls;
   hipStream_t st;
   hipEvent_t a = nullptr;
+  cpppl_ctx::SpanState state{0, false};
+  cpppl_ctx::SpanState* outer = nullptr;
   Span(cpppl_ctx* c_, int cls_, hipStream_t s_ = nullptr) : c(c_), cls(cls_), st(s_ ? s_ : c_->stream) {
     if (c->timing) {
       a = next_event(c);
       CPPPL_HIP(hipEventRecord(a, st));
+      state.cls = cls;
+      outer = c->span;
+      c->span = &state;
     }
   }
   ~Span() noexcept(false) {
     if (c->timing && a) {
+      c->span = outer;
+      if (state.has_sub) return;  // the launches of a cut product were timed one by one
       hipEvent_t b = next_event(c);
       CPPPL_HIP(hipEventRecord(b, st));
-      c->segs.push_back({cls, a, b});
+      c->segs.push_back({cls, a, b, 1});
+    }
+  }
+};
+
+// Times one launch of a product cut into several (inside a class span), so
+// that side-stream work dispatched between the launches is not counted.
+struct LaunchSpan {
+  cpppl_ctx* c;
+  hipEvent_t a = nullptr;
+  int calls;
+  LaunchSpan(cpppl_ctx* c_, bool first) : c(c_), calls(first ? 1 : 0) {
+    if (c->timing && c->span) {
+      a = next_event(c);
+      CPPPL_HIP(hipEventRecord(a, c->stream));
+    }
+  }
+  ~LaunchSpan() noexcept(false) {
+    if (a) {
+      hipEvent_t b = next_event(c);
+      CPPPL_HIP(hipEventRecord(b, c->stream));
+      c->segs.push_back({c->span->cls, a, b, calls});
+      c->span->has_sub = true;
     }
   }
 };
@@ -226,9 +257,50 @@ Path path_for(cpppl_ctx* c, DType dt) {
   return P;
 }
 
-void run_gemm(const Path& P, const Gemm& g, hipStream_t s) {
-  if (P.dt == DType::F64) gemm_f64(g, s);
-  else gemm_bf16(g, s);
+// Inverse steps queued on the side stream are dispatched only between
+// main-stream launches (a grid with work-groups still to place keeps the CUs),
+// so while a side inverse is pending an unsplit BF16 product is cut into
+// c->launch_chunks launches along its batch, else along N in whole tiles.
+// Measured at o=32, v=256, X=768, R=1024: four launches per product raise the
+// sweep rate by 4 %, because the inverse then waits less at its join.
+void run_gemm(cpppl_ctx* c, const Path& P, const Gemm& g) {
+  hipStream_t s = c->stream;
+  const int k = c->launch_chunks;
+  if (P.dt == DType::F64) {
+    gemm_f64(g, s);
+    return;
+  }
+  if (k <= 1 || g.splits > 1) {
+    gemm_bf16(g, s);
+    return;
+  }
+  const int64_t ea = 2, eb = g.b_fp8 ? 1 : 2;
+  const int64_t ec = g.ctype == DType::BF16 ? 2 : (g.ctype == DType::F32 ? 4 : 8);
+  if (g.batch >= k && !g.b_fp8) {
+    const int64_t per = (g.batch + k - 1) / k;
+    for (int64_t b0 = 0; b0 < g.batch; b0 += per) {
+      Gemm h = g;
+      h.batch = std::min(per, g.batch - b0);
+      h.A = (const char*)g.A + b0 * g.sab * ea;
+      h.B = (const char*)g.B + b0 * g.sbb * eb;
+      h.C = (char*)g.C + b0 * g.scb * ec;
+      LaunchSpan ls(c, b0 == 0);
+      gemm_bf16(h, s);
+    }
+  } else if (g.batch == 1 && g.N >= 128 * k) {
+    const int64_t per = ((g.N + k - 1) / k + 127) / 128 * 128;
+    for (int64_t n0 = 0; n0 < g.N; n0 += per) {
+      Gemm h = g;
+      h.N = std::min(per, g.N - n0);
+      h.B = (const char*)g.B + n0 * g.sbn * eb;
+      h.C = (char*)g.C + n0 * ec;
+      if (g.b_fp8 && g.bscale_mode == 1) h.bscale = g.bscale + n0;
+      LaunchSpan ls(c, n0 == 0);
+      gemm_bf16(h, s);
+    }
+  } else {
+    gemm_bf16(g, s);
+  }
 }
 
 int splits_for(cpppl_ctx* c, const Path& P, int64_t M, int64_t N, int64_t K, int64_t batch) {
@@ -253,7 +325,7 @@ void compute_tau(cpppl_ctx* c, const Path& P) {
   g.A = c->at(c->plan.Kt); g.sam = o * o; g.sak = 1;
   g.B = P.T2T; g.sbn = o * o; g.sbk = 1; g.b_fp8 = P.fp8;
   g.C = c->at(c->plan.tau); g.scm = v * v; g.ctype = P.dt;
-  run_gemm(P, g, c->stream);
+  run_gemm(c, P, g);
 }
 
 // Y[r][X][q] = sum_p F[r][p] B^X_pq for F = factor `mode` (2 alpha with B,
@@ -268,7 +340,7 @@ void compute_Y(cpppl_ctx* c, const Path& P, int mode, size_t out) {
   g.B = bside ? P.BnT_b : P.BnT; g.sbn = v; g.sbk = 1;
   g.b_fp8 = P.fp8; g.bscale = bside ? P.sBx_b : P.sBx; g.bscale_mode = 1;  // n = (X, q)
   g.C = c->at(out); g.scm = X * v; g.ctype = P.dt;
-  run_gemm(P, g, c->stream);
+  run_gemm(c, P, g);
 }
 
 // Z for mode a (contract d with tau[r][c][d]) or b (contract c).
@@ -281,7 +353,7 @@ void compute_Z(cpppl_ctx* c, const Path& P, int mode) {
   g.B = c->at(c->plan.tau); g.sbb = v * v;
   if (mode == 2) { g.sbn = v; g.sbk = 1; } else { g.sbk = v; g.sbn = 1; }
   g.C = c->at(c->plan.Z); g.scm = v; g.scb = X * v; g.ctype = P.dt;
-  run_gemm(P, g, c->stream);
+  run_gemm(c, P, g);
 }
 
 // M^T[r][p] = sum_{X,q} Z[r][X][q] B^X_pq  -> MT (FP64); mode 3 (beta)
@@ -298,7 +370,7 @@ void compute_M(cpppl_ctx* c, const Path& P, int mode) {
   g.C = c->at(c->plan.MT); g.scm = v; g.ctype = DType::F64;
   g.splits = splits_for(c, P, g.M, g.N, g.K, 1);
   g.partial = c->at(c->plan.partial);
-  run_gemm(P, g, c->stream);
+  run_gemm(c, P, g);
 }
 
 // G[r][c][d] = sum_X Ya[r][X][c] Yb[r][X][d]   (stored in the Z buffer)
@@ -310,7 +382,7 @@ void compute_G(cpppl_ctx* c, const Path& P) {
   g.A = c->at(c->plan.Ya); g.sam = 1; g.sak = v; g.sab = X * v;
   g.B = c->at(c->plan.Yb); g.sbk = v; g.sbn = 1; g.sbb = X * v;
   g.C = c->at(c->plan.Z); g.scm = v; g.scb = v * v; g.ctype = P.dt;
-  run_gemm(P, g, c->stream);
+  run_gemm(c, P, g);
 }
 
 // H^T[r][ij] = sum_cd G[r][cd] t[ij][cd]  -> HT (FP64)
@@ -325,7 +397,7 @@ void compute_H(cpppl_ctx* c, const Path& P) {
   g.C = c->at(c->plan.HT); g.scm = o * o; g.ctype = DType::F64;
   g.splits = splits_for(c, P, g.M, g.N, g.K, 1);
   g.partial = c->at(c->plan.partial);
-  run_gemm(P, g, c->stream);
+  run_gemm(c, P, g);
 }
 
 void compute_occ(cpppl_ctx* c, int mode) {
@@ -496,13 +568,13 @@ void compute_eta(cpppl_ctx* c) {
     Gemm g;
     g.M = R; g.N = R; g.K = n;
     g.A = c->at(p.FT[m]); g.sam = n; g.sak = 1;
-    g.B = c->at(p.FTprev[m]); g.sbn = n; g.sbk = 1;
+    g.B = c->at(p.FTprev[c->snap][m]); g.sbn = n; g.sbk = 1;
     g.C = c->at(p.cross[m]); g.scm = R; g.ctype = DType::F64;
     gemm_f64(g, c->stream);
     X[m] = c->at<double>(p.cross[m]);
   }
   double* sc = c->at<double>(p.scal);
-  weighted_hadamard_sum(X, c->at<double>(p.lam), c->at<double>(p.lamprev), R,
+  weighted_hadamard_sum(X, c->at<double>(p.lam), c->at<double>(p.lamprev[c->snap]), R,
                         c->at<double>(p.rowbuf), sc + S_ETA + 1, c->stream);
   // sc[S_ETA] = nn = cp2 of this sweep, sc[S_ETA+2] = pp = cp2 of the previous state
   CPPPL_HIP(hipMemcpyAsync(sc + S_ETA, sc + S_FIT + 1, 8, hipMemcpyDeviceToDevice, c->stream));
@@ -534,32 +606,36 @@ size_t factor_set_bytes(const cpppl_ctx* c) {
   return (size_t)((2 * c->d.o + 2 * c->d.v) * c->d.rank + c->d.rank) * 8;
 }
 
-void snapshot(cpppl_ctx* c) {
+// Factors and weights into snapshot slot `slot`, which becomes the eta
+// reference of the next sweep.
+void snapshot(cpppl_ctx* c, int slot) {
   const Plan& p = c->plan;
+  c->snap = slot;
   const int64_t R = c->d.rank;
   const double* src[5];
   double* dst[5];
   int64_t n[5];
   for (int m = 0; m < 4; ++m) {
     src[m] = c->at<double>(p.FT[m]);
-    dst[m] = c->at<double>(p.FTprev[m]);
+    dst[m] = c->at<double>(p.FTprev[slot][m]);
     n[m] = nmode(c->d, m) * R;
   }
   src[4] = c->at<double>(p.lam);
-  dst[4] = c->at<double>(p.lamprev);
+  dst[4] = c->at<double>(p.lamprev[slot]);
   n[4] = R;
   copy_doubles(src, dst, n, 5, c->stream);
 }
 
-void restore_snapshot(cpppl_ctx* c) {
+void restore_snapshot(cpppl_ctx* c, int slot) {
   const Plan& p = c->plan;
+  c->snap = slot;
   const int64_t R = c->d.rank;
   for (int m = 0; m < 4; ++m) {
-    copy_d2d(c, p.FT[m], p.FTprev[m], (size_t)(nmode(c->d, m) * R) * 8);
+    copy_d2d(c, p.FT[m], p.FTprev[slot][m], (size_t)(nmode(c->d, m) * R) * 8);
     compute_gram(c, m);
     refresh_lowp(c, m);
   }
-  copy_d2d(c, p.lam, p.lamprev, (size_t)R * 8);
+  copy_d2d(c, p.lam, p.lamprev[slot], (size_t)R * 8);
   c->ybeta_valid = false;
 }
 
@@ -608,6 +684,11 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful) {
     // fork mark), but its ~20 launches are issued by the host only after the
     // mode's first two main-stream kernels are queued, so the main queue does
     // not wait on the host issuing them.
+    struct Chunked {
+      cpppl_ctx* c;
+      explicit Chunked(cpppl_ctx* x) : c(x) { c->launch_chunks = 4; }
+      ~Chunked() { c->launch_chunks = 1; }
+    } chunked(c);
     mark_fork(c);
     compute_tau(c, P);
     if (!c->ybeta_valid || c->ybeta_dt != P.dt) compute_Y(c, P, 3, p.Yb);
@@ -976,14 +1057,18 @@ CPPPL_API cpppl_status cpppl_create(const cpppl_dims* dims, cpppl_precision prec
   c->stream = (hipStream_t)hip_stream;
   c->plan = build_plan(*dims, prec);
   if (hipSetDevice(device) != hipSuccess ||
-      hipHostMalloc((void**)&c->host_scal, S_COUNT * sizeof(double) + 16 * sizeof(int),
+      hipHostMalloc((void**)&c->host_scal, 2 * (S_COUNT * sizeof(double) + 16 * sizeof(int)),
                     hipHostMallocDefault) != hipSuccess ||
       hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_done[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_done[1], hipEventDisableTiming) != hipSuccess) {
     if (c->host_scal) (void)hipHostFree(c->host_scal);
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->ev_main) (void)hipEventDestroy(c->ev_main);
+    if (c->ev_side) (void)hipEventDestroy(c->ev_side);
+    if (c->ev_done[0]) (void)hipEventDestroy(c->ev_done[0]);
     delete c;
     return CPPPL_E_HIP;
   }
@@ -1018,6 +1103,8 @@ CPPPL_API cpppl_status cpppl_destroy(cpppl_ctx* c) {
   }
   if (c->ev_main) (void)hipEventDestroy(c->ev_main);
   if (c->ev_side) (void)hipEventDestroy(c->ev_side);
+  for (hipEvent_t e : c->ev_done)
+    if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   delete c;
@@ -1296,48 +1383,81 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
   const DType main_dt = c->prec != CPPPL_FP64 ? DType::BF16 : DType::F64;
   const int total = opts->max_sweeps + (c->prec != CPPPL_FP64 ? opts->refine_fp64_sweeps : 0);
   double prev_fit = std::numeric_limits<double>::quiet_NaN();
-  auto t_start = std::chrono::steady_clock::now();
   sync(c);
-  t_start = std::chrono::steady_clock::now();
+  const auto t_start = std::chrono::steady_clock::now();
+  auto t_prev = t_start;
   bool stop_main = false;
-  for (int s = 0; s < total; ++s) {
-    const bool refining = s >= opts->max_sweeps;
-    if (!refining && stop_main) continue;
-    const Path P = path_for(c, refining ? DType::F64 : main_dt);
-    auto ts = std::chrono::steady_clock::now();
-    snapshot(c);
+  // A sweep is issued before the host reads the previous sweep's results, so
+  // the GPU does not idle while the host checks a fit or a pivot status.  A
+  // sweep issued past a stop, or after a sweep whose pivot failed, is rolled
+  // back from its snapshot.  (With the near-optimal cache, whose ring holds
+  // the last six iterates, sweeps are issued one at a time.)
+  const bool ahead = !opts->near_cache;
+  auto next_of = [&](int s) {
+    if (s < opts->max_sweeps && stop_main) s = opts->max_sweeps;
+    return s < total ? s : -1;
+  };
+  auto path_of = [&](int s) { return path_for(c, s >= opts->max_sweeps ? DType::F64 : main_dt); };
+  const size_t slot_bytes = S_COUNT * 8 + 16 * sizeof(int);
+  auto host_slot = [&](int k) { return c->host_scal + (size_t)k * (S_COUNT + 8); };
+  // sweep s with its snapshot in the other slot; its scalars and status go to
+  // that slot's host buffer, marked by ev_done[slot]
+  auto issue = [&](int s) {
+    const int slot = c->snap ^ 1;
+    snapshot(c, slot);
     zero_ints(c->at<int>(p.status), 1, c->stream);
-    int retries = sweep(c, P, false);
-    // scalars and status in one copy (status directly follows the scalar block)
-    CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(p.scal), S_COUNT * 8 + 16 * sizeof(int),
-                             hipMemcpyDeviceToHost, c->stream));
-    sync(c);
-    if (c->host_status[0]) {  // a Cholesky pivot failed: redo this sweep with ridge retries
-      restore_snapshot(c);
-      CPPPL_HIP(hipMemcpyAsync(c->at<double>(p.scal) + S_CP2_PREV, &c->host_scal[S_ETA + 2], 8,
+    (void)sweep(c, path_of(s), false);
+    if (opts->near_cache)
+      copy_factor_set(c, p.nearRing + (size_t)(rep->sweeps_done % 6) * factor_set_bytes(c), true);
+    CPPPL_HIP(hipMemcpyAsync(host_slot(slot), c->at(p.scal), slot_bytes, hipMemcpyDeviceToHost,
+                             c->stream));
+    CPPPL_HIP(hipEventRecord(c->ev_done[slot], c->stream));
+    return slot;
+  };
+  int cur = next_of(0);
+  int cur_slot = cur >= 0 ? issue(cur) : 0;
+  while (cur >= 0) {
+    int nxt = ahead ? next_of(cur + 1) : -1;
+    const int nxt_slot = nxt >= 0 ? issue(nxt) : 0;
+    CPPPL_HIP(hipEventSynchronize(c->ev_done[cur_slot]));
+    double* hs = host_slot(cur_slot);
+    int retries = 0;
+    if (((const int*)(hs + S_COUNT))[0]) {
+      // a Cholesky pivot failed: drop the sweep issued after this one and redo
+      // this sweep from its snapshot with ridge retries
+      sync(c);
+      nxt = -1;
+      restore_snapshot(c, cur_slot);
+      CPPPL_HIP(hipMemcpyAsync(c->at<double>(p.scal) + S_CP2_PREV, hs + S_ETA + 2, 8,
                                hipMemcpyHostToDevice, c->stream));
-      retries = sweep(c, P, true);
-      CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(p.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
+      retries = sweep(c, path_of(cur), true);
+      if (opts->near_cache)
+        copy_factor_set(c, p.nearRing + (size_t)(rep->sweeps_done % 6) * factor_set_bytes(c), true);
+      CPPPL_HIP(hipMemcpyAsync(hs, c->at(p.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
       sync(c);
     }
+    const bool refining = cur >= opts->max_sweeps;
     rep->ridge_retries += retries;
-    const double fit = c->host_scal[S_FIT + 3];
-    const double eta = c->want_eta ? c->host_scal[S_ETA + 3] : std::numeric_limits<double>::quiet_NaN();
-    if (!std::isfinite(fit) || !std::isfinite(c->host_scal[S_FIT + 1]))
-      throw StatusError(CPPPL_E_NONFINITE, "non-finite fit after sweep " + std::to_string(s + 1));
-    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ts).count();
+    const double fit = hs[S_FIT + 3];
+    const double eta = c->want_eta ? hs[S_ETA + 3] : std::numeric_limits<double>::quiet_NaN();
+    if (!std::isfinite(fit) || !std::isfinite(hs[S_FIT + 1])) {
+      sync(c);
+      throw StatusError(CPPPL_E_NONFINITE, "non-finite fit after sweep " + std::to_string(cur + 1));
+    }
+    const auto t_now = std::chrono::steady_clock::now();
+    const double ms = std::chrono::duration<double, std::milli>(t_now - t_prev).count();
+    t_prev = t_now;
     if (rep->fit_hist && rep->sweeps_done < opts->history_cap) rep->fit_hist[rep->sweeps_done] = fit;
     if (rep->eta_hist && rep->sweeps_done < opts->history_cap) rep->eta_hist[rep->sweeps_done] = eta;
     if (rep->ms_hist && rep->sweeps_done < opts->history_cap) rep->ms_hist[rep->sweeps_done] = ms;
-    if (opts->near_cache)
-      copy_factor_set(c, p.nearRing + (size_t)(rep->sweeps_done % 6) * factor_set_bytes(c), true);
     rep->sweeps_done++;
     if (refining) rep->refine_done++;
     rep->fit = fit;
     rep->eta = eta;
-    rep->inner = c->host_scal[S_FIT + 0];
-    rep->cp_norm2 = c->host_scal[S_FIT + 1];
-    rep->loss = c->host_scal[S_FIT + 4];
+    rep->inner = hs[S_FIT + 0];
+    rep->cp_norm2 = hs[S_FIT + 1];
+    rep->loss = hs[S_FIT + 4];
+    bool done = false;
     if (!refining) {
       main_fits.push_back(fit);
       const size_t nf = main_fits.size();
@@ -1346,10 +1466,26 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
         stop_main = true;
       if (opts->stop_rule == 2 && eta < opts->tol) stop_main = true;
     } else if (opts->refine_tol > 0.0 && std::fabs(fit - prev_fit) < opts->refine_tol) {
-      prev_fit = fit;
-      break;
+      done = true;
     }
     prev_fit = fit;
+    const int want = done ? -1 : next_of(cur + 1);
+    if (nxt >= 0 && nxt != want) {
+      // the sweep issued ahead is past a stop: back to the state after this
+      // sweep (factors from the next snapshot, scalars from this readback)
+      sync(c);
+      restore_snapshot(c, nxt_slot);
+      CPPPL_HIP(hipMemcpyAsync(c->at(p.scal), hs, S_COUNT * 8, hipMemcpyHostToDevice, c->stream));
+      sync(c);
+      nxt = -1;
+    }
+    if (nxt < 0 && want >= 0) {
+      cur = want;
+      cur_slot = issue(cur);
+    } else {
+      cur = nxt;
+      cur_slot = nxt_slot;
+    }
   }
   if (opts->near_cache && rep->sweeps_done > 5) {  // the (n-5)th iterate becomes the cache
     const size_t sb = factor_set_bytes(c);
@@ -1368,7 +1504,7 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
       float ms = 0.f;
       CPPPL_HIP(hipEventElapsedTime(&ms, sg.a, sg.b));
       rep->ms_class[sg.cls] += ms;
-      rep->n_class[sg.cls] += 1;
+      rep->n_class[sg.cls] += sg.calls;
     }
     c->segs.clear();
     c->timing = false;

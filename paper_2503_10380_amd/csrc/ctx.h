@@ -24,7 +24,8 @@ struct Plan {
   // Dbar with the same layouts and copies as B
   size_t t2raw, t1, bvo, bb64, bb64T, bb64P, bb16T, bb16P, bb8T, bb8P, sBb, sBbx;
   // factors (transposed, R x n), weights, snapshots, Grams
-  size_t FT[4], FTprev[4], F16T[4], lam, lamprev;
+  size_t FT[4], F16T[4], lam;
+  size_t FTprev[2][4], lamprev[2];  // two snapshot slots: the states before the last two sweeps
   size_t gram[4], cross[4], invA, invB, invD, MT, stage, nearRing, nearCache;
   // intermediates: one region [tau | Ya | Yb | Z]; G aliases Z
   size_t big, tau, Ya, Yb, Z;
@@ -93,17 +94,25 @@ struct cpppl_ctx {
 
   hipStream_t side = nullptr;     // inverse of W overlapped with the MTTKRP chain
   hipEvent_t ev_main = nullptr, ev_side = nullptr;
+  hipEvent_t ev_done[2] = {nullptr, nullptr};  // a sweep's results reached host_scal slot k
+  int launch_chunks = 1;  // launches per unsplit BF16 product (more while a side inverse is pending)
+  int snap = 0;  // snapshot slot holding the state before the most recently issued sweep
   double* inv = nullptr;          // buffer holding -W^{-1} of the last prepared mode
 
-  double* host_scal = nullptr;  // pinned: S_COUNT doubles followed by the 16 status ints
+  double* host_scal = nullptr;  // pinned, two slots of S_COUNT doubles + 16 status ints
   int* host_status = nullptr;   // = (int*)(host_scal + S_COUNT)
 
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  struct Seg { int cls; hipEvent_t a, b; };
+  // timed spans of a class; `calls` is 1 for the span that counts the call
+  // (a product cut into several launches gives one span per launch, the first
+  // counting the call)
+  struct Seg { int cls; hipEvent_t a, b; int calls; };
   std::vector<Seg> segs;
+  struct SpanState { int cls; bool has_sub; };
+  SpanState* span = nullptr;  // innermost open class span
 
   template <typename T = void>
   T* at(size_t off) { return (T*)(ws + off); }
