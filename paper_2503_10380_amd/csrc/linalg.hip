@@ -5,8 +5,9 @@
 //   A_ik <- A_ik D,  A_kj <- D A_kj,  A_kk <- -D
 // After every block has been swept once, A holds -A^{-1}.
 //
-// One launch per block step, one work-group per 64 x 64 output tile, two
-// matrix buffers alternating so no launch reads what it writes.  The pivot
+// One launch per block step, one work-group per 64 x 64 output tile of the
+// upper triangle (it also writes the mirror tile), two matrix buffers
+// alternating so no launch reads what it writes.  The pivot
 // inverse is looked ahead: the work-group whose output tile is the next
 // diagonal block (dispatched first) inverts that tile right after computing it
 // and publishes D for the next launch, so each 64 x 64 inverse is done once per
@@ -368,9 +369,23 @@ __global__ __launch_bounds__(256) void first_pivot_kernel(const double* __restri
   slab_store(p, Dout);
 }
 
+// Tiles (I, J) with I <= J of a T x T tile grid, numbered row by row.
+__device__ __forceinline__ int64_t upper_index(int64_t I, int64_t J, int64_t T) {
+  return I * T - I * (I - 1) / 2 + (J - I);
+}
+__device__ __forceinline__ void upper_coords(int64_t u, int64_t T, int64_t& I, int64_t& J) {
+  I = 0;
+  while (u >= T - I) {
+    u -= T - I;
+    ++I;
+  }
+  J = I + u;
+}
+
 // One block step of the sweep; Dk = A_kk^{-1} (NB x NB) comes from the previous
-// launch.  The group whose output is diagonal block k + 1 also inverts that
-// block into Dnext.
+// launch.  The swept matrix stays symmetric, so one group computes tile (I, J)
+// for I <= J and also writes its transpose to (J, I).  The group whose output
+// is diagonal block k + 1 also inverts that block into Dnext.
 __global__ __launch_bounds__(256, 2) void sweep_kernel(const double* __restrict__ A,
                                                     double* __restrict__ O,
                                                     const double* __restrict__ Dk,
@@ -380,11 +395,11 @@ __global__ __launch_bounds__(256, 2) void sweep_kernel(const double* __restrict_
   __shared__ double T1[T1_SIZE];  // A_Ik, then A_Ik D; the pivot inverse's scratch
   const int tid = threadIdx.x, lane = tid & 63, wn = (tid >> 6) & 1;
   const int64_t T = (R + NB - 1) / NB;
-  const int64_t nt = T * T;
+  const int64_t nu = T * (T + 1) / 2;
   // the next pivot's group is dispatched first
-  const int64_t first = (kb + 1 < T) ? (kb + 1) * T + kb + 1 : 0;
-  const int64_t t = (blockIdx.x + first) % nt;
-  const int64_t I = t / T, J = t % T;
+  const int64_t first = (kb + 1 < T) ? upper_index(kb + 1, kb + 1, T) : 0;
+  int64_t I, J;
+  upper_coords((blockIdx.x + first) % nu, T, I, J);
   const int64_t k0 = kb * NB, i0 = I * NB, j0 = J * NB;
   const int nk = (int)min((int64_t)NB, R - k0);
   const int ni = (int)min((int64_t)NB, R - i0);
@@ -457,6 +472,20 @@ __global__ __launch_bounds__(256, 2) void sweep_kernel(const double* __restrict_
     mfma_mm_rb<true>(T1, LD, bf, out);
   }
   rt_store(out, O + i0 * R + j0, R, ni, nj);
+  if (I != J) {  // the mirror tile (J, I), transposed through LDS for row-wise stores
+    __syncthreads();  // every lane has read T1
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) T1[rt_col(j) * LD + rt_row(i, r)] = out.v[i][j][r];
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int r = e / NB, cc = e % NB;
+      if (r < nj && cc < ni) O[(j0 + r) * R + i0 + cc] = T1[r * LD + cc];
+    }
+  }
 
   if (I == kb + 1 && J == kb + 1) {  // look ahead: invert the next pivot block
     __syncthreads();                 // T1 is free: move the tile into the slab layout
@@ -507,8 +536,8 @@ double* spd_inverse_neg(double* bufA, double* bufB, double* dbuf, int64_t R, int
   for (int64_t kb = 0; kb < T; ++kb) {
     const double* dk = dbuf + (kb & 1) * NB * NB;
     double* dn = dbuf + ((kb + 1) & 1) * NB * NB;
-    hipLaunchKernelGGL(sweep_kernel, dim3((unsigned)(T * T)), dim3(256), 0, s, in, out, dk, dn, R,
-                       kb, status);
+    hipLaunchKernelGGL(sweep_kernel, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, in, out,
+                       dk, dn, R, kb, status);
     CPPPL_LAUNCH_CHECK("sweep");
     std::swap(in, out);
   }
