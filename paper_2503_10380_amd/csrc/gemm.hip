@@ -193,6 +193,14 @@ __global__ __launch_bounds__(256, BM > 64 ? 2 : 1) void gemm_f64_kernel(const KA
 constexpr int BBK_SHORT = 32, BBK_LONG = 64;
 constexpr int64_t BBK_LONG_MIN_K = 2048;
 
+// 16 aligned bytes as one vector load (a plain uint4 copy can be lowered to a
+// memcpy through private memory).
+__device__ __forceinline__ uint4 load16(const bf16_t* p) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 v = *(const u32x4*)p;
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
 // 8 bf16 at p[0], p[step], ... with the elements at index >= count set to 0.
 __device__ __forceinline__ uint4 gather8(const bf16_t* p, int64_t step, int64_t count) {
   uint32_t w[4];
@@ -238,13 +246,26 @@ struct BfTile {
     const int swz = BBK == 32 ? (row >> 1) & 3 : row & 7;
     return row * BLDK + (((kk >> 3) ^ swz) << 3);
   }
+  // FAST: every 16-byte chunk of the slice lies inside K (K a multiple of the
+  // slice) and is aligned; rows past the end are clamped to the last row
+  // (the last aligned group of 8 for a row-contiguous operand, whose row count
+  // is then a multiple of 8): they only feed results that are not stored.
+  template <bool FAST = false>
   __device__ __forceinline__ static void load(uint4 (&r)[C], const bf16_t* X, int64_t s_row,
                                               int64_t s_k, int64_t row0, int64_t nrows, int64_t k0,
                                               int64_t kend, bool vec, int tid) {
 #pragma unroll
     for (int e = 0; e < C; ++e) {
       const int c = tid + e * NT;
-      if (KC) {
+      if constexpr (FAST && KC) {
+        const int row = c / (BBK / 8), kk = (c % (BBK / 8)) * 8;
+        const int64_t g = min(row0 + row, nrows - 1);
+        r[e] = load16(X + g * s_row + k0 + kk);
+      } else if constexpr (FAST) {
+        const int kk = c / (ROWS / 8), row = (c % (ROWS / 8)) * 8;
+        const int64_t g = min(row0 + row, nrows - 8);
+        r[e] = load16(X + (k0 + kk) * s_k + g);
+      } else if (KC) {
         const int row = c / (BBK / 8), kk = (c % (BBK / 8)) * 8;
         const int64_t g = row0 + row, gk = k0 + kk;
         const bf16_t* p = X + g * s_row + gk;
@@ -352,10 +373,12 @@ template <> __device__ __forceinline__ double to_out<double>(float v) { return (
 // per CU) or 8 waves (256 x 128 tiles, two per CU: each operand element staged
 // in LDS then feeds 256 or 128 products instead of 128, a quarter less LDS
 // writing and L2 reading per flop at the same 64 x 64 tile per wave).
-template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT, bool B8 = false, int WGM = 2>
+template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT, bool B8 = false, int WGM = 2,
+          bool FAST = false>
 __global__ __launch_bounds__(128 * WGM, WGM == 4 ? 4 : (BBK == BBK_LONG ? 2 : ((AK && BKC && !B8 && sizeof(OutT) <= 4) ? 4 : 3)))
 void gemm_bf16_kernel(const KArgs a) {
   static_assert(!B8 || BKC, "an e4m3 B operand must be k-contiguous");
+  static_assert(!(FAST && B8), "e4m3 B operands take the checked loads");
   static_assert(WGM == 2 || (WGM == 4 && BBK == BBK_SHORT && AK && BKC && !B8),
                 "8-wave tiles: k-contiguous BF16 operands, short slices");
   constexpr int NT = 128 * WGM;
@@ -400,9 +423,9 @@ void gemm_bf16_kernel(const KArgs a) {
 
   const int64_t nk = kend > kbeg ? (kend - kbeg + BBK - 1) / BBK : 0;
   if (nk > 0) {
-    TA::load(ra, A, sa_row, sa_k, m0, a.M, kbeg, kend, vec, tid);
+    TA::template load<FAST>(ra, A, sa_row, sa_k, m0, a.M, kbeg, kend, vec, tid);
     if constexpr (B8) T8::load(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, kbeg, kend, vec, a, tid);
-    else TB::load(rb, B, sb_row, sb_k, n0, a.N, kbeg, kend, vec, tid);
+    else TB::template load<FAST>(rb, B, sb_row, sb_k, n0, a.N, kbeg, kend, vec, tid);
     TA::store(ra, As, tid);
     if constexpr (B8) T8::store(r8, Bs, tid);
     else TB::store(rb, Bs, tid);
@@ -428,8 +451,8 @@ void gemm_bf16_kernel(const KArgs a) {
   if constexpr (DEEP) {
     uint4 ra2[TA::C], rb2[TB::C];
     if (nk > 1) {
-      TA::load(ra2, A, sa_row, sa_k, m0, a.M, kbeg + BBK, kend, vec, tid);
-      TB::load(rb2, B, sb_row, sb_k, n0, a.N, kbeg + BBK, kend, vec, tid);
+      TA::template load<FAST>(ra2, A, sa_row, sa_k, m0, a.M, kbeg + BBK, kend, vec, tid);
+      TB::template load<FAST>(rb2, B, sb_row, sb_k, n0, a.N, kbeg + BBK, kend, vec, tid);
     }
     __syncthreads();
     // slice kt sits in LDS buffer kt % 2; register stage kt % 2 is free and
@@ -439,8 +462,8 @@ void gemm_bf16_kernel(const KArgs a) {
       const int cur = (int)(kt & 1);
       if (kt + 2 < nk) {
         const int64_t k2 = kbeg + (kt + 2) * BBK;
-        TA::load(la, A, sa_row, sa_k, m0, a.M, k2, kend, vec, tid);
-        TB::load(lb, B, sb_row, sb_k, n0, a.N, k2, kend, vec, tid);
+        TA::template load<FAST>(la, A, sa_row, sa_k, m0, a.M, k2, kend, vec, tid);
+        TB::template load<FAST>(lb, B, sb_row, sb_k, n0, a.N, k2, kend, vec, tid);
       }
       mma(As + cur * AS, Bs + cur * BS);
       if (kt + 1 < nk) {
@@ -461,9 +484,9 @@ void gemm_bf16_kernel(const KArgs a) {
     const bf16_t* Bc = Bs + cur * BS;
     if (kt + 1 < nk) {
       const int64_t k1 = kbeg + (kt + 1) * BBK;
-      TA::load(ra, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
+      TA::template load<FAST>(ra, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
       if constexpr (B8) T8::load(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, k1, kend, vec, a, tid);
-      else TB::load(rb, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
+      else TB::template load<FAST>(rb, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
     }
     mma(Ac, Bc);
     if (kt + 1 < nk) {
@@ -684,25 +707,25 @@ void gemm_f64(const Gemm& g, hipStream_t s) {
   if (a.splits > 1) launch_reduce<double, double>(a, s);
 }
 
-template <int BK, bool AK, bool BKC, bool B8 = false, int WGM = 2>
+template <int BK, bool AK, bool BKC, bool B8 = false, int WGM = 2, bool FAST = false>
 static void launch_bf16(const KArgs& a, DType ct, dim3 grid, hipStream_t s) {
   constexpr int BM = 64 * WGM, BN = 128;
   const dim3 block(128 * WGM);
   if (ct == DType::F32 || a.splits > 1)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, float, B8, WGM>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, float, B8, WGM, FAST>), grid, block, 0, s, a);
   else if (ct == DType::BF16)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, bf16_t, B8, WGM>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, bf16_t, B8, WGM, FAST>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, double, B8, WGM>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BM, BN, BK, AK, BKC, double, B8, WGM, FAST>), grid, block, 0, s, a);
 }
 
-template <int BK>
+template <int BK, bool FAST>
 static void launch_bf16_layout(const KArgs& a, bool ak, bool bk, DType ct, dim3 grid,
                                hipStream_t s) {
-  if (ak && bk) launch_bf16<BK, true, true>(a, ct, grid, s);
-  else if (ak && !bk) launch_bf16<BK, true, false>(a, ct, grid, s);
-  else if (!ak && bk) launch_bf16<BK, false, true>(a, ct, grid, s);
-  else launch_bf16<BK, false, false>(a, ct, grid, s);
+  if (ak && bk) launch_bf16<BK, true, true, false, 2, FAST>(a, ct, grid, s);
+  else if (ak && !bk) launch_bf16<BK, true, false, false, 2, FAST>(a, ct, grid, s);
+  else if (!ak && bk) launch_bf16<BK, false, true, false, 2, FAST>(a, ct, grid, s);
+  else launch_bf16<BK, false, false, false, 2, FAST>(a, ct, grid, s);
 }
 
 void gemm_bf16(const Gemm& g, hipStream_t s) {
@@ -744,12 +767,20 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
       if (ak) launch_bf16<BBK_SHORT, true, true, true>(a, g.ctype, grid, s);
       else launch_bf16<BBK_SHORT, false, true, true>(a, g.ctype, grid, s);
     }
-  } else if (BM == 256) {
-    launch_bf16<BBK_SHORT, true, true, false, 4>(a, g.ctype, grid, s);
-  } else if (bk_slice == BBK_LONG) {
-    launch_bf16_layout<BBK_LONG>(a, ak, bk, g.ctype, grid, s);
   } else {
-    launch_bf16_layout<BBK_SHORT>(a, ak, bk, g.ctype, grid, s);
+    // unchecked loads when every slice is whole and every chunk aligned
+    const bool fast = a.vec_ok && g.K % bk_slice == 0 && (ak || g.M % 8 == 0) &&
+                      (bk || g.N % 8 == 0);
+    if (BM == 256) {
+      if (fast) launch_bf16<BBK_SHORT, true, true, false, 4, true>(a, g.ctype, grid, s);
+      else launch_bf16<BBK_SHORT, true, true, false, 4>(a, g.ctype, grid, s);
+    } else if (bk_slice == BBK_LONG) {
+      if (fast) launch_bf16_layout<BBK_LONG, true>(a, ak, bk, g.ctype, grid, s);
+      else launch_bf16_layout<BBK_LONG, false>(a, ak, bk, g.ctype, grid, s);
+    } else {
+      if (fast) launch_bf16_layout<BBK_SHORT, true>(a, ak, bk, g.ctype, grid, s);
+      else launch_bf16_layout<BBK_SHORT, false>(a, ak, bk, g.ctype, grid, s);
+    }
   }
   CPPPL_LAUNCH_CHECK("gemm_bf16");
   if (a.splits > 1) {

@@ -62,6 +62,9 @@ CASES = [
     (257, 129, 9000, 2, 2),     # BF16: K slices of 64 per split, ragged tail
     (512, 130, 1100, 1, 1),     # BF16 k-contiguous: 256-row tiles, ragged K tail
     (2100, 70, 1040, 2, 1),     # BF16 k-contiguous: 256-row tiles, ragged last tile row
+    (200, 136, 256, 2, 1),      # BF16 unchecked loads: whole K slices, ragged rows (multiples of 8)
+    (200, 136, 4096, 1, 1),     # the same with K slices of 64
+    (264, 72, 8192, 1, 2),      # the same, split-K
 ]
 
 
