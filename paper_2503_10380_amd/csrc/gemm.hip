@@ -369,13 +369,16 @@ template <> __device__ __forceinline__ float to_out<float>(float v) { return v; 
 template <> __device__ __forceinline__ bf16_t to_out<bf16_t>(float v) { return f32_to_bf16(v); }
 template <> __device__ __forceinline__ double to_out<double>(float v) { return (double)v; }
 
-// WGM wave rows by 2 wave columns: 4 waves (128 x 128 tiles, 3 or 4 work-groups
-// per CU) or 8 waves (256 x 128 tiles, two per CU: each operand element staged
-// in LDS then feeds 256 or 128 products instead of 128, a quarter less LDS
-// writing and L2 reading per flop at the same 64 x 64 tile per wave).
+// Waves per SIMD (work-groups per CU for 128 x 128 tiles): 4 where the
+// registers fit in 128 (two k-contiguous operands, or two row-contiguous ones
+// with unchecked loads, 2- or 4-byte results), else 3; 2 for K slices of 64.
+// WGM wave rows by 2 wave columns: 4 waves (128 x 128 tiles) or 8 waves
+// (256 x 128 tiles, two per CU: each operand element staged in LDS then feeds
+// 256 or 128 products instead of 128, a quarter less LDS writing and L2
+// reading per flop at the same 64 x 64 tile per wave).
 template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT, bool B8 = false, int WGM = 2,
           bool FAST = false>
-__global__ __launch_bounds__(128 * WGM, WGM == 4 ? 4 : (BBK == BBK_LONG ? 2 : ((AK && BKC && !B8 && sizeof(OutT) <= 4) ? 4 : 3)))
+__global__ __launch_bounds__(128 * WGM, WGM == 4 ? 4 : (BBK == BBK_LONG ? 2 : ((((AK && BKC) || (FAST && !AK && !BKC)) && !B8 && sizeof(OutT) <= 4) ? 4 : 3)))
 void gemm_bf16_kernel(const KArgs a) {
   static_assert(!B8 || BKC, "an e4m3 B operand must be k-contiguous");
   static_assert(!(FAST && B8), "e4m3 B operands take the checked loads");
