@@ -453,9 +453,13 @@ void gemm_bf16_kernel(const KArgs a) {
   };
   if constexpr (DEEP) {
     uint4 ra2[TA::C], rb2[TB::C];
-    if (nk > 1) {
-      TA::template load<FAST>(ra2, A, sa_row, sa_k, m0, a.M, kbeg + BBK, kend, vec, tid);
-      TB::template load<FAST>(rb2, B, sb_row, sb_k, n0, a.N, kbeg + BBK, kend, vec, tid);
+    // With unchecked loads the slice index is clamped instead of the loads
+    // being skipped past the end (a repeated last slice is never stored):
+    // loads issued on every path let the compiler wait for one stage only.
+    if (FAST || nk > 1) {
+      const int64_t k1 = kbeg + (FAST ? min((int64_t)1, nk - 1) : 1) * BBK;
+      TA::template load<FAST>(ra2, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
+      TB::template load<FAST>(rb2, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
     }
     __syncthreads();
     // slice kt sits in LDS buffer kt % 2; register stage kt % 2 is free and
@@ -463,8 +467,8 @@ void gemm_bf16_kernel(const KArgs a) {
     auto step = [&](int64_t kt, uint4 (&la)[TA::C], uint4 (&lb)[TB::C], uint4 (&sa)[TA::C],
                     uint4 (&sb)[TB::C]) {
       const int cur = (int)(kt & 1);
-      if (kt + 2 < nk) {
-        const int64_t k2 = kbeg + (kt + 2) * BBK;
+      if (FAST || kt + 2 < nk) {
+        const int64_t k2 = kbeg + (FAST ? min(kt + 2, nk - 1) : kt + 2) * BBK;
         TA::template load<FAST>(la, A, sa_row, sa_k, m0, a.M, k2, kend, vec, tid);
         TB::template load<FAST>(lb, B, sb_row, sb_k, n0, a.N, k2, kend, vec, tid);
       }
@@ -475,10 +479,16 @@ void gemm_bf16_kernel(const KArgs a) {
       }
       __syncthreads();
     };
-    for (int64_t kt = 0; kt < nk; kt += 2) {
+    // Both steps run on every trip, so the loads in flight at the top of a
+    // trip are always those into the second stage: the compiler then does not
+    // wait for them before issuing the first stage's loads (a loop that could
+    // come back after one step made it wait for every load in flight).
+    int64_t kt = 0;
+    for (; kt + 1 < nk; kt += 2) {
       step(kt, ra, rb, ra2, rb2);
-      if (kt + 1 < nk) step(kt + 1, ra2, rb2, ra, rb);
+      step(kt + 1, ra2, rb2, ra, rb);
     }
+    if (kt < nk) step(kt, ra, rb, ra2, rb2);
   } else {
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
