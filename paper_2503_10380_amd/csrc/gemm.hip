@@ -372,13 +372,17 @@ template <> __device__ __forceinline__ double to_out<double>(float v) { return (
 // Waves per SIMD (work-groups per CU for 128 x 128 tiles): 4 where the
 // registers fit in 128 (two k-contiguous operands, or two row-contiguous ones
 // with unchecked loads, 2- or 4-byte results), else 3; 2 for K slices of 64.
+template <bool AK, bool BKC, bool B8, bool FAST, typename OutT>
+constexpr bool four_waves() {
+  return ((AK && BKC) || (FAST && !AK && !BKC)) && !B8 && sizeof(OutT) <= 4;
+}
 // WGM wave rows by 2 wave columns: 4 waves (128 x 128 tiles) or 8 waves
 // (256 x 128 tiles, two per CU: each operand element staged in LDS then feeds
 // 256 or 128 products instead of 128, a quarter less LDS writing and L2
 // reading per flop at the same 64 x 64 tile per wave).
 template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT, bool B8 = false, int WGM = 2,
           bool FAST = false>
-__global__ __launch_bounds__(128 * WGM, WGM == 4 ? 4 : (BBK == BBK_LONG ? 2 : ((((AK && BKC) || (FAST && !AK && !BKC)) && !B8 && sizeof(OutT) <= 4) ? 4 : 3)))
+__global__ __launch_bounds__(128 * WGM, WGM == 4 ? 4 : (BBK == BBK_LONG ? 2 : (four_waves<AK, BKC, B8, FAST, OutT>() ? 4 : 3)))
 void gemm_bf16_kernel(const KArgs a) {
   static_assert(!B8 || BKC, "an e4m3 B operand must be k-contiguous");
   static_assert(!(FAST && B8), "e4m3 B operands take the checked loads");
@@ -433,9 +437,13 @@ void gemm_bf16_kernel(const KArgs a) {
     if constexpr (B8) T8::store(r8, Bs, tid);
     else TB::store(rb, Bs, tid);
   }
-  // Long K slices (two work-groups per CU) keep a second register stage so the
-  // global loads of slice k + 2 are in flight while slice k is multiplied.
-  constexpr bool DEEP = BBK == BBK_LONG && !B8;
+  // A second register stage keeps the global loads of slice k + 2 in flight
+  // while slice k is multiplied: for long K slices (two work-groups per CU),
+  // and on the unchecked path where it costs no occupancy (256-row tiles, and
+  // 128 x 128 tiles already at three waves per SIMD).  Measured on MI355X, it
+  // costs more than it gains where it would take a fourth wave away.
+  constexpr bool DEEP =
+      !B8 && (BBK == BBK_LONG || (FAST && (WGM == 4 || !four_waves<AK, BKC, B8, FAST, OutT>())));
   auto mma = [&](const bf16_t* Ac, const bf16_t* Bc) {
 #pragma unroll
     for (int ks = 0; ks < BBK; ks += 32) {
@@ -782,7 +790,7 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
     }
   } else {
     // unchecked loads when every slice is whole and every chunk aligned
-    const bool fast = a.vec_ok && g.K % bk_slice == 0 && (ak || g.M % 8 == 0) &&
+    const bool fast = a.vec_ok && g.K > 0 && g.K % bk_slice == 0 && (ak || g.M % 8 == 0) &&
                       (bk || g.N % 8 == 0);
     if (BM == 256) {
       if (fast) launch_bf16<BBK_SHORT, true, true, false, 4, true>(a, g.ctype, grid, s);
