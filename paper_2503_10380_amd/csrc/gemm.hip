@@ -331,6 +331,8 @@ struct F8Tile {
       r.s[e] = (a.bscale_mode == 1 && g < nrows) ? a.bscale[g] : 1.0f;
     }
   }
+  // FAST as for BfTile::load: whole aligned chunks, rows clamped.
+  template <bool FAST = false>
   __device__ __forceinline__ static void load(Regs& r, const uint8_t* X, int64_t s_row, int64_t row0,
                                               int64_t nrows, int64_t k0, int64_t kend, bool vec,
                                               const KArgs& a, int tid) {
@@ -338,9 +340,13 @@ struct F8Tile {
     for (int e = 0; e < C; ++e) {
       const int c = tid + e * 256;
       const int row = c / (BBK / 8), kk = (c % (BBK / 8)) * 8;
-      const int64_t g = row0 + row, gk = k0 + kk;
+      const int64_t g = FAST ? min(row0 + row, nrows - 1) : row0 + row, gk = k0 + kk;
       const uint8_t* p = X + g * s_row + gk;
-      if (vec && g < nrows && gk + 8 <= kend) {
+      if constexpr (FAST) {
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 v = *(const u32x2*)p;
+        r.q[e] = make_uint2(v[0], v[1]);
+      } else if (vec && g < nrows && gk + 8 <= kend) {
         r.q[e] = *(const uint2*)p;
       } else {
         const int64_t cnt = g < nrows ? kend - gk : 0;
@@ -350,7 +356,7 @@ struct F8Tile {
           if (q < cnt) w[q >> 2] |= (uint32_t)p[q] << (8 * (q & 3));
         r.q[e] = make_uint2(w[0], w[1]);
       }
-      if (a.bscale_mode == 2) r.s[e] = gk < kend ? a.bscale[gk] : 1.0f;
+      if (a.bscale_mode == 2) r.s[e] = (FAST || gk < kend) ? a.bscale[gk] : 1.0f;
     }
   }
   __device__ __forceinline__ static void store(const Regs& r, bf16_t* S, int tid) {
@@ -385,7 +391,6 @@ template <int BM, int BN, int BBK, bool AK, bool BKC, typename OutT, bool B8 = f
 __global__ __launch_bounds__(128 * WGM, WGM == 4 ? 4 : (BBK == BBK_LONG ? 2 : (four_waves<AK, BKC, B8, FAST, OutT>() ? 4 : 3)))
 void gemm_bf16_kernel(const KArgs a) {
   static_assert(!B8 || BKC, "an e4m3 B operand must be k-contiguous");
-  static_assert(!(FAST && B8), "e4m3 B operands take the checked loads");
   static_assert(WGM == 2 || (WGM == 4 && BBK == BBK_SHORT && AK && BKC && !B8),
                 "8-wave tiles: k-contiguous BF16 operands, short slices");
   constexpr int NT = 128 * WGM;
@@ -431,7 +436,7 @@ void gemm_bf16_kernel(const KArgs a) {
   const int64_t nk = kend > kbeg ? (kend - kbeg + BBK - 1) / BBK : 0;
   if (nk > 0) {
     TA::template load<FAST>(ra, A, sa_row, sa_k, m0, a.M, kbeg, kend, vec, tid);
-    if constexpr (B8) T8::load(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, kbeg, kend, vec, a, tid);
+    if constexpr (B8) T8::template load<FAST>(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, kbeg, kend, vec, a, tid);
     else TB::template load<FAST>(rb, B, sb_row, sb_k, n0, a.N, kbeg, kend, vec, tid);
     TA::store(ra, As, tid);
     if constexpr (B8) T8::store(r8, Bs, tid);
@@ -506,7 +511,7 @@ void gemm_bf16_kernel(const KArgs a) {
     if (kt + 1 < nk) {
       const int64_t k1 = kbeg + (kt + 1) * BBK;
       TA::template load<FAST>(ra, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
-      if constexpr (B8) T8::load(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, k1, kend, vec, a, tid);
+      if constexpr (B8) T8::template load<FAST>(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, k1, kend, vec, a, tid);
       else TB::template load<FAST>(rb, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
     }
     mma(Ac, Bc);
@@ -780,18 +785,22 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
   if (blocks == 0) return;
   if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_bf16: grid too large");
   dim3 grid((unsigned)blocks);
+  // unchecked loads when every slice is whole and every chunk aligned
+  const bool fast = a.vec_ok && g.K > 0 && g.K % bk_slice == 0 && (ak || g.M % 8 == 0) &&
+                    (bk || g.N % 8 == 0);
   if (g.b_fp8) {
     if (bk_slice == BBK_LONG) {
-      if (ak) launch_bf16<BBK_LONG, true, true, true>(a, g.ctype, grid, s);
+      if (ak && fast) launch_bf16<BBK_LONG, true, true, true, 2, true>(a, g.ctype, grid, s);
+      else if (ak) launch_bf16<BBK_LONG, true, true, true>(a, g.ctype, grid, s);
+      else if (fast) launch_bf16<BBK_LONG, false, true, true, 2, true>(a, g.ctype, grid, s);
       else launch_bf16<BBK_LONG, false, true, true>(a, g.ctype, grid, s);
     } else {
-      if (ak) launch_bf16<BBK_SHORT, true, true, true>(a, g.ctype, grid, s);
+      if (ak && fast) launch_bf16<BBK_SHORT, true, true, true, 2, true>(a, g.ctype, grid, s);
+      else if (ak) launch_bf16<BBK_SHORT, true, true, true>(a, g.ctype, grid, s);
+      else if (fast) launch_bf16<BBK_SHORT, false, true, true, 2, true>(a, g.ctype, grid, s);
       else launch_bf16<BBK_SHORT, false, true, true>(a, g.ctype, grid, s);
     }
   } else {
-    // unchecked loads when every slice is whole and every chunk aligned
-    const bool fast = a.vec_ok && g.K > 0 && g.K % bk_slice == 0 && (ak || g.M % 8 == 0) &&
-                      (bk || g.N % 8 == 0);
     if (BM == 256) {
       if (fast) launch_bf16<BBK_SHORT, true, true, false, 4, true>(a, g.ctype, grid, s);
       else launch_bf16<BBK_SHORT, true, true, false, 4>(a, g.ctype, grid, s);
