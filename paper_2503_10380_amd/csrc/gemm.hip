@@ -625,8 +625,18 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const PT* __restrict
   const int64_t total = batch * M * N;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
+    // loads in groups of eight so they are in flight together; the sum
+    // still runs in split order
     double acc = 0.0;
-    for (int s = 0; s < splits; ++s) acc += (double)part[s * total + idx];
+    int s = 0;
+    for (; s + 8 <= splits; s += 8) {
+      PT v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = part[(s + q) * total + idx];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += (double)v[q];
+    }
+    for (; s < splits; ++s) acc += (double)part[s * total + idx];
     const int64_t b = idx / (M * N), rem = idx % (M * N);
     const int64_t m = rem / N, n = rem % N;
     OutT* c = C + b * scb + m * scm + n;
