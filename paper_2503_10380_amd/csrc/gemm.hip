@@ -729,7 +729,13 @@ static void launch_f64(const KArgs& a, bool ak, bool bk, dim3 grid, hipStream_t 
 void gemm_f64(const Gemm& g, hipStream_t s) {
   check_operand_strides(g);
   if (g.ctype != DType::F64) throw std::invalid_argument("gemm_f64: output must be FP64");
-  const int T = f64_tile_m(g.M, g.N);
+  int T = f64_tile_m(g.M, g.N);
+  // a launch of fewer than 256 128-row work-groups leaves CUs idle: take
+  // 64-row tiles instead (the R x R Gram products)
+  if (T == 128) {
+    const int64_t blocks128 = ((g.M + 127) / 128) * ((g.N + 63) / 64) * g.batch * std::max(1, g.splits);
+    if (blocks128 < 256) T = 64;
+  }
   KArgs a = make_args(g, T, 64, 16);
   if (a.splits > 1 && !a.partial) throw std::invalid_argument("gemm_f64: split-K needs a partial buffer");
   const int64_t blocks = a.tiles_m * a.tiles_n * a.batch * a.splits;
