@@ -512,10 +512,18 @@ void apply_inverse(cpppl_ctx* c, int m) {
   const int64_t cap = (int64_t)(p.partial_elems / (size_t)(R * n));
   g.splits = (int)std::max<int64_t>(1, std::min<int64_t>(s, cap));
   g.partial = c->at(p.partial);
-  gemm_f64(g, c->stream);
-  row_normalize(c->at<double>(p.FT[m]), R, n, c->at<double>(p.lam), c->stream);
+  g.keep_partials = true;  // summed below, unless K was not split
+  const int used = gemm_f64(g, c->stream);
+  if (used > 1) {
+    // the split sum, the normalisation and the BF16 copy in one launch
+    finish_factor(c->at<double>(p.partial), used, R, n, g.alpha, c->at<double>(p.FT[m]),
+                  c->at<double>(p.lam), c->prec != CPPPL_FP64 ? c->at(p.F16T[m]) : nullptr,
+                  c->stream);
+  } else {
+    row_normalize(c->at<double>(p.FT[m]), R, n, c->at<double>(p.lam), c->stream);
+    refresh_lowp(c, m);
+  }
   compute_gram(c, m);
-  refresh_lowp(c, m);
 }
 
 int solve_mode(cpppl_ctx* c, int m, bool careful) {

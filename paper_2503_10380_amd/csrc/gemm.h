@@ -28,6 +28,9 @@ struct Gemm {
   double alpha = 1.0, beta = 0.0;
   int splits = 1;
   void* partial = nullptr;
+  // gemm_f64 only: with splits > 1, leave the partial products in `partial`
+  // (splits x batch x M x N, split-major) for the caller to sum; C is not written.
+  bool keep_partials = false;
   // gemm_bf16 only: B holds OCP e4m3 codes (one byte each, k-contiguous),
   // dequantised to bfloat16 on the way into LDS and multiplied by a scale
   // (exact for power-of-two scales): bscale_mode 0 none, 1 bscale[n] (per
@@ -37,8 +40,9 @@ struct Gemm {
   int bscale_mode = 0;
 };
 
-// A and B in FP64, accumulation in FP64 (v_mfma_f64_16x16x4f64).
-void gemm_f64(const Gemm& g, hipStream_t s);
+// A and B in FP64, accumulation in FP64 (v_mfma_f64_16x16x4f64).  Returns
+// the number of K splits used (at most g.splits: K is cut in whole slices).
+int gemm_f64(const Gemm& g, hipStream_t s);
 // A and B in bfloat16 (B optionally e4m3, see Gemm::b_fp8), accumulation in
 // FP32 (v_mfma_f32_16x16x32_bf16); beta must be 0 unless split.
 void gemm_bf16(const Gemm& g, hipStream_t s);

@@ -726,7 +726,7 @@ static void launch_f64(const KArgs& a, bool ak, bool bk, dim3 grid, hipStream_t 
   else hipLaunchKernelGGL((gemm_f64_kernel<T, 64, false, false>), grid, block, 0, s, a);
 }
 
-void gemm_f64(const Gemm& g, hipStream_t s) {
+int gemm_f64(const Gemm& g, hipStream_t s) {
   check_operand_strides(g);
   if (g.ctype != DType::F64) throw std::invalid_argument("gemm_f64: output must be FP64");
   int T = f64_tile_m(g.M, g.N);
@@ -739,14 +739,15 @@ void gemm_f64(const Gemm& g, hipStream_t s) {
   KArgs a = make_args(g, T, 64, 16);
   if (a.splits > 1 && !a.partial) throw std::invalid_argument("gemm_f64: split-K needs a partial buffer");
   const int64_t blocks = a.tiles_m * a.tiles_n * a.batch * a.splits;
-  if (blocks == 0) return;
+  if (blocks == 0) return a.splits;
   if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_f64: grid too large");
   const bool ak = g.sak == 1, bk = g.sbk == 1;
   dim3 grid((unsigned)blocks);
   if (T == 128) launch_f64<128>(a, ak, bk, grid, s);
   else launch_f64<64>(a, ak, bk, grid, s);
   CPPPL_LAUNCH_CHECK("gemm_f64");
-  if (a.splits > 1) launch_reduce<double, double>(a, s);
+  if (a.splits > 1 && !g.keep_partials) launch_reduce<double, double>(a, s);
+  return a.splits;
 }
 
 template <int BK, bool AK, bool BKC, bool B8 = false, int WGM = 2, bool FAST = false>

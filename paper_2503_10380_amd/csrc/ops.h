@@ -42,6 +42,12 @@ void hadamard(const double* g1, const double* g2, const double* g3, double* w, i
               hipStream_t s);
 // lam[r] = ||FT[r][:]||_2, FT[r][:] /= lam[r] (rows with zero norm are left as they are).
 void row_normalize(double* FT, int64_t R, int64_t n, double* lam, hipStream_t s);
+// FT[r] = alpha * sum_s part[s][r] (split order), then row_normalize, then (if
+// lowp) the BF16 copy: one launch for the split-K reduction, the
+// normalisation and the conversion that follow the factor solve, with the same
+// arithmetic in the same order as those three steps.
+void finish_factor(const double* part, int splits, int64_t R, int64_t n, double alpha, double* FT,
+                   double* lam, void* lowp, hipStream_t s);
 // Occupied-mode reductions of HT[r][i*o + j]:
 //   which = 0: M[r][i] = sum_j HT[r][i*o+j] * other[r][j]   (gamma update)
 //   which = 1: M[r][j] = sum_i HT[r][i*o+j] * other[r][i]   (rho update)

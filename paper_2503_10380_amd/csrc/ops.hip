@@ -200,6 +200,33 @@ __global__ __launch_bounds__(TPB) void row_normalize_kernel(double* FT, int64_t 
   }
 }
 
+__global__ __launch_bounds__(TPB) void finish_factor_kernel(const double* __restrict__ part,
+                                                             int splits, int64_t R, int64_t n,
+                                                             double alpha, double* FT, double* lam,
+                                                             void* lowp) {
+  __shared__ double sh[TPB];
+  const int64_t r = blockIdx.x;
+  double* row = FT + r * n;
+  const int64_t stride = R * n;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += TPB) {
+    double acc = 0.0;
+    for (int q = 0; q < splits; ++q) acc += part[q * stride + r * n + i];
+    const double v = alpha * acc;
+    row[i] = v;
+    s += v * v;
+  }
+  s = block_sum(s, sh);
+  const double nrm = sqrt(s);
+  if (threadIdx.x == 0) lam[r] = nrm;
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
+  for (int64_t i = threadIdx.x; i < n; i += TPB) {
+    const double v = nrm > 0.0 ? row[i] * inv : row[i];
+    row[i] = v;
+    if (lowp) put_dt(lowp, DType::BF16, r * n + i, v);
+  }
+}
+
 __global__ void occ_reduce_kernel(const double* __restrict__ HT, const double* __restrict__ other,
                                   double* M, int64_t o, int64_t R, int which) {
   const int64_t total = R * o;
@@ -532,6 +559,14 @@ void hadamard(const double* g1, const double* g2, const double* g3, double* w, i
 void row_normalize(double* FT, int64_t R, int64_t n, double* lam, hipStream_t s) {
   hipLaunchKernelGGL(row_normalize_kernel, dim3((unsigned)R), dim3(TPB), 0, s, FT, n, lam);
   CPPPL_LAUNCH_CHECK("row_normalize");
+}
+
+void finish_factor(const double* part, int splits, int64_t R, int64_t n, double alpha, double* FT,
+                   double* lam, void* lowp, hipStream_t s) {
+  if (R <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(finish_factor_kernel, dim3((unsigned)R), dim3(TPB), 0, s, part, splits, R, n,
+                     alpha, FT, lam, lowp);
+  CPPPL_LAUNCH_CHECK("finish_factor");
 }
 
 void occ_reduce(const double* HT, const double* other, double* M, int64_t o, int64_t R, int which,

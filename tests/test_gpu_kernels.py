@@ -65,6 +65,9 @@ CASES = [
     (200, 136, 256, 2, 1),      # BF16 unchecked loads: whole K slices, ragged rows (multiples of 8)
     (200, 136, 4096, 1, 1),     # the same with K slices of 64
     (264, 72, 8192, 1, 2),      # the same, split-K
+    (136, 200, 2112, 1, 1),     # unchecked loads, two-stage prefetch over an odd number of 64-deep slices
+    (200, 136, 96, 1, 1),       # unchecked loads, three 32-deep slices (two-stage where the layout runs at three waves)
+    (200, 136, 32, 2, 1),       # unchecked loads, a single slice
 ]
 
 
@@ -102,6 +105,7 @@ STAGED = [
     (768, 256, 1100, 1, 1),     # 256-row tiles, ragged K tail
     (2100, 130, 1030, 1, 1),    # 256-row tiles, ragged last tile row
     (512, 200, 96, 2, 1),       # 128-row tiles, short K
+    (512, 136, 1056, 1, 1),     # 256-row tiles, two-stage prefetch over an odd number of slices
     (1024, 64, 3000, 1, 4),     # 128-row tiles, split-K
 ]
 
