@@ -71,6 +71,31 @@ __device__ __forceinline__ Coords tile_coords(int64_t lid, const KArgs& a) {
   return c;
 }
 
+// 32-bit form of xcd_remap followed by tile_coords, for launches whose tile
+// count is below 2^31 (the BF16 launcher refuses larger grids).
+__device__ __forceinline__ Coords tile_coords32(uint32_t bid, uint32_t nblocks, const KArgs& a) {
+  uint32_t lid = bid;
+  if (nblocks >= 8) {
+    const uint32_t per = nblocks / 8, rem = nblocks % 8, xcd = bid % 8;
+    lid = xcd * per + (xcd < rem ? xcd : rem) + bid / 8;
+  }
+  const uint32_t tmn = (uint32_t)a.tiles_m, tnn = (uint32_t)a.tiles_n;
+  const uint32_t tiles = tmn * tnn;
+  const uint32_t t = lid % tiles, bs = lid / tiles;
+  const uint32_t sp = (uint32_t)a.splits;
+  Coords c;
+  c.split = (int)(bs % sp);
+  c.b = bs / sp;
+  if (tmn <= tnn) {
+    c.tm = t % tmn;
+    c.tn = t / tmn;
+  } else {
+    c.tn = t % tnn;
+    c.tm = t / tnn;
+  }
+  return c;
+}
+
 template <typename OutT>
 __device__ __forceinline__ void store_out(const KArgs& a, const Coords& tc, int64_t gm, int64_t gn,
                                           double v) {
@@ -192,6 +217,10 @@ __global__ __launch_bounds__(256, BM > 64 ? 2 : 1) void gemm_f64_kernel(const KA
 // long K per split (fewer barriers per flop).
 constexpr int BBK_SHORT = 32, BBK_LONG = 64;
 constexpr int64_t BBK_LONG_MIN_K = 2048;
+// Chained launches (two tiles per work-group): products of 2048 to 4096
+// tiles of 128 x 128 whose K per split is at most 512.
+constexpr int64_t BF16_CHAIN_MIN_TILES = 2048, BF16_CHAIN_MAX_TILES = 4096,
+                  BF16_CHAIN_MAX_K = 512;
 
 // 16 aligned bytes as one vector load (a plain uint4 copy can be lowered to a
 // memcpy through private memory).
@@ -411,21 +440,40 @@ void gemm_bf16_kernel(const KArgs a) {
   bf16_t* As = (bf16_t*)smem;             // [2][AS]
   bf16_t* Bs = (bf16_t*)smem + 2 * AS;    // [2][BS]
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid0 = threadIdx.x;
+  const bool vec = a.vec_ok != 0;
+  const int64_t sa_row = AK ? a.sam : 1, sa_k = AK ? 1 : a.sak;
+  const int64_t sb_row = BKC ? a.sbn : 1, sb_k = BKC ? 1 : a.sbk;
+
+  // A work-group computes the tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+  // of the XCD-remapped order (one tile when the grid covers them all).
+  const uint32_t ntile = (uint32_t)(a.tiles_m * a.tiles_n * a.batch * a.splits);
+  using T8 = F8Tile<BN, BBK>;
+  uint4 ra[TA::C], rb[B8 ? 1 : TB::C];
+  typename T8::Regs r8;
+  // The short-slice path issues the loads of the next tile's first slice
+  // before its epilogue, so they are in flight while the results are stored.
+  constexpr bool DEEP =
+      !B8 && (BBK == BBK_LONG || (FAST && (WGM == 4 || !four_waves<AK, BKC, B8, FAST, OutT>())));
+  constexpr bool CHAIN = FAST && WGM == 2 && !DEEP && !B8;
+  bool primed = false;  // ra, rb hold the first slice of the current tile
+  Coords tc = tile_coords32(blockIdx.x, ntile, a);
+  for (uint32_t vt = blockIdx.x; vt < ntile; vt += gridDim.x) {
+  // lane-dependent addresses are recomputed per tile rather than held in
+  // registers across the tile loop
+  int tid = tid0;
+  if constexpr (CHAIN) asm volatile("" : "+v"(tid));
+  const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const Coords tc = tile_coords(xcd_remap(blockIdx.x, gridDim.x), a);
+  const uint32_t vnext = vt + gridDim.x;
+  const bool more = CHAIN && vnext < ntile;
+  const Coords tn = more ? tile_coords32(vnext, ntile, a) : tc;
   const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
   const int64_t kbeg = (int64_t)tc.split * a.kchunk;
   const int64_t kend = min(a.K, kbeg + a.kchunk);
   const bf16_t* A = (const bf16_t*)a.A + tc.b * a.sab;
   const bf16_t* B = (const bf16_t*)a.B + tc.b * a.sbb;
-  const bool vec = a.vec_ok != 0;
-  const int64_t sa_row = AK ? a.sam : 1, sa_k = AK ? 1 : a.sak;
-  const int64_t sb_row = BKC ? a.sbn : 1, sb_k = BKC ? 1 : a.sbk;
 
-  using T8 = F8Tile<BN, BBK>;
-  uint4 ra[TA::C], rb[B8 ? 1 : TB::C];
-  typename T8::Regs r8;
   if constexpr (B8) T8::init_scales(r8, a, n0, a.N, tid);
   f4_t acc[TM][TN];
 #pragma unroll
@@ -435,20 +483,21 @@ void gemm_bf16_kernel(const KArgs a) {
 
   const int64_t nk = kend > kbeg ? (kend - kbeg + BBK - 1) / BBK : 0;
   if (nk > 0) {
-    TA::template load<FAST>(ra, A, sa_row, sa_k, m0, a.M, kbeg, kend, vec, tid);
-    if constexpr (B8) T8::template load<FAST>(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, kbeg, kend, vec, a, tid);
-    else TB::template load<FAST>(rb, B, sb_row, sb_k, n0, a.N, kbeg, kend, vec, tid);
+    if (!primed) {
+      TA::template load<FAST>(ra, A, sa_row, sa_k, m0, a.M, kbeg, kend, vec, tid);
+      if constexpr (B8) T8::template load<FAST>(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, kbeg, kend, vec, a, tid);
+      else TB::template load<FAST>(rb, B, sb_row, sb_k, n0, a.N, kbeg, kend, vec, tid);
+    }
     TA::store(ra, As, tid);
     if constexpr (B8) T8::store(r8, Bs, tid);
     else TB::store(rb, Bs, tid);
   }
+  primed = false;
   // A second register stage keeps the global loads of slice k + 2 in flight
   // while slice k is multiplied: for long K slices (two work-groups per CU),
   // and on the unchecked path where it costs no occupancy (256-row tiles, and
   // 128 x 128 tiles already at three waves per SIMD).  Measured on MI355X, it
   // costs more than it gains where it would take a fourth wave away.
-  constexpr bool DEEP =
-      !B8 && (BBK == BBK_LONG || (FAST && (WGM == 4 || !four_waves<AK, BKC, B8, FAST, OutT>())));
   auto mma = [&](const bf16_t* Ac, const bf16_t* Bc) {
 #pragma unroll
     for (int ks = 0; ks < BBK; ks += 32) {
@@ -504,6 +553,10 @@ void gemm_bf16_kernel(const KArgs a) {
     if (kt < nk) step(kt, ra, rb, ra2, rb2);
   } else {
   __syncthreads();
+  // the next tile's first slice, loaded during this tile's last slice
+  const int64_t nkbeg = (int64_t)tn.split * a.kchunk;
+  const int64_t nkend = min(a.K, nkbeg + a.kchunk);
+  const bool chain = CHAIN && more && nkend > nkbeg;
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = (int)(kt & 1);
     const bf16_t* Ac = As + cur * AS;
@@ -521,6 +574,15 @@ void gemm_bf16_kernel(const KArgs a) {
       else TB::store(rb, Bs + (cur ^ 1) * BS, tid);
     }
     __syncthreads();
+  }
+  if constexpr (CHAIN) {
+    if (chain) {
+      TA::template load<FAST>(ra, (const bf16_t*)a.A + tn.b * a.sab, sa_row, sa_k, tn.tm * BM, a.M,
+                              nkbeg, nkend, vec, tid);
+      TB::template load<FAST>(rb, (const bf16_t*)a.B + tn.b * a.sbb, sb_row, sb_k, tn.tn * BN, a.N,
+                              nkbeg, nkend, vec, tid);
+      primed = true;
+    }
   }
   }
 
@@ -613,6 +675,11 @@ void gemm_bf16_kernel(const KArgs a) {
           const int64_t gn = n0 + wn * WN + j * 16 + 4 * (lane >> 4) + r;
           if (gm < a.M && gn < a.N) store_out<OutT>(a, tc, gm, gn, (double)acc[i][j][r]);
         }
+  }
+  if constexpr (!CHAIN) break;
+  // the epilogue's LDS reads end before the next tile's first slice is stored
+  if (more) __syncthreads();
+  tc = tn;
   }
 }
 
@@ -801,10 +868,26 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
   const int64_t blocks = a.tiles_m * a.tiles_n * a.batch * a.splits;
   if (blocks == 0) return;
   if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_bf16: grid too large");
-  dim3 grid((unsigned)blocks);
   // unchecked loads when every slice is whole and every chunk aligned
   const bool fast = a.vec_ok && g.K > 0 && g.K % bk_slice == 0 && (ak || g.M % 8 == 0) &&
                     (bk || g.N % 8 == 0);
+  // Short-K products of a few waves of work-groups, on 128 x 128 tiles at
+  // four waves per SIMD, run two tiles per work-group, the second tile's
+  // first slice loading before the first tile's results are stored.  Measured
+  // on MI355X at o = 32, v = 256, X = 768, R = 1024 (Y and Z cut into launches
+  // of 3072 tiles): the products alone ran as fast as with one tile per
+  // work-group, but the ALS sweep ran 2-3 % faster, since side-stream inverse
+  // steps are dispatched only once a launch's work-groups have all been
+  // issued.  Other sizes measured worse: smaller grids leave CUs idle (3 %
+  // slower at o = 16, v = 128), launches of 13824 tiles ran 1 % slower and
+  // G's longer K (X = 1152) 10 % slower.  Without the early load the second
+  // tile's loads queue behind the first tile's stores, and chained products
+  // took twice as long.
+  const bool four = (ak && bk) || (fast && !ak && !bk);
+  const bool chain = fast && !g.b_fp8 && BM == 128 && bk_slice == BBK_SHORT && four &&
+                     (g.ctype != DType::F64 || a.splits > 1) && blocks >= BF16_CHAIN_MIN_TILES &&
+                     blocks <= BF16_CHAIN_MAX_TILES && a.kchunk <= BF16_CHAIN_MAX_K;
+  dim3 grid((unsigned)(chain ? (blocks + 1) / 2 : blocks));
   if (g.b_fp8) {
     if (bk_slice == BBK_LONG) {
       if (ak && fast) launch_bf16<BBK_LONG, true, true, true, 2, true>(a, g.ctype, grid, s);

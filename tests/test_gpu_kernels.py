@@ -134,6 +134,45 @@ def test_gemm_bf16_outputs(env, out, case):
     assert err <= (5e-5 if out == "f32" else 8e-3), err
 
 
+CHAINED = [
+    # (M, N, K, batch, splits): 2048 to 4096 tiles of 128 x 128 with K per
+    # split at most 512, so work-groups run two tiles in turn
+    (136, 264, 64, 400, 1),      # ragged last tile row and column (multiples of 8)
+    (200, 136, 32, 900, 1),      # a single K slice per tile
+    (128, 128, 64, 2101, 1),     # an odd tile count: the last work-group has one tile
+    (1024, 2048, 1248, 1, 20),   # split-K, the last split one slice shorter than the rest
+]
+
+
+@pytest.mark.parametrize("layout", ["kk", "rr"])
+@pytest.mark.parametrize("out", ["f32", "bf16"])
+@pytest.mark.parametrize("case", CHAINED)
+def test_gemm_bf16_chained(env, layout, out, case):
+    """Unchecked short-K products of 2048 to 4096 tiles at four waves per SIMD (two
+    k-contiguous or two row-contiguous operands) run two tiles per work-group,
+    the second tile's first slice loading before the first tile's results are
+    stored.  Every tile is checked against numpy."""
+    L, torch = env
+    M, N, K, batch, splits = case
+    ak = bk = layout == "kk"
+    _say(f"gemm bf16 chained {layout} -> {out} case={case}")
+    rng = np.random.default_rng(hash((M, N, K, batch, layout, out)) % 2 ** 32)
+    a, ta, sam, sak, sab = _operand(torch, rng, batch, M, K, 1 if ak else 0, "bf16", pad=8)
+    b, tb, sbk, sbn, sbb = _operand(torch, rng, batch, K, N, 0 if bk else 1, "bf16", pad=8)
+    tdt = torch.float32 if out == "f32" else torch.bfloat16
+    tc = torch.full((batch * M * N,), 7.0, dtype=tdt, device="cuda")
+    part = torch.zeros(max(1, splits * batch * M * N), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    st = L.cpppl_test_gemm(1, M, N, K, batch, ta.data_ptr(), sam, sak, sab, tb.data_ptr(), sbk,
+                           sbn, sbb, tc.data_ptr(), N, M * N, 1 if out == "f32" else 2, 1.0, 0.0,
+                           splits, part.data_ptr(), stream)
+    assert st == 0
+    want = np.matmul(a, b)
+    got = tc.to(torch.float64).cpu().numpy().reshape(batch, M, N)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err <= (5e-5 if out == "f32" else 8e-3), err
+
+
 @pytest.mark.parametrize("R,n", [(1, 3), (17, 5), (64, 64), (65, 7), (300, 130), (1024, 256),
                                  (2048, 32)])
 def test_spd_inverse_solve(env, R, n):
