@@ -173,6 +173,51 @@ def test_gemm_bf16_chained(env, layout, out, case):
     assert err <= (5e-5 if out == "f32" else 8e-3), err
 
 
+@pytest.mark.parametrize("which", ["Y", "Z"])
+def test_gemm_bf16_chained_bitwise(env, which):
+    """At o = 32, v = 256, X = 768, R = 1024 the ALS sweep cuts Y = F^T B and
+    Z = Y tau (per r) into four launches of 3072 tiles, which run two tiles per
+    work-group; a whole product (12288 tiles) runs one per work-group.  Each
+    tile's arithmetic is the same, so the two must agree bit for bit."""
+    L, torch = env
+    v, X, R = 256, 768, 1024
+    _say(f"gemm bf16 chained vs whole, {which} at v={v} X={X} R={R}")
+    g = torch.Generator(device="cuda").manual_seed(7)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def call(M, N, K, batch, A, sam, sak, sab, B, sbk, sbn, sbb, C, scm, scb):
+        st = L.cpppl_test_gemm(1, M, N, K, batch, A, sam, sak, sab, B, sbk, sbn, sbb, C, scm, scb,
+                               2, 1.0, 0.0, 1, 0, stream)
+        assert st == 0
+
+    if which == "Y":
+        M, N, K = R, X * v, v
+        a = torch.randn(M * K, device="cuda", generator=g).to(torch.bfloat16)   # [r][p]
+        b = torch.randn(N * K, device="cuda", generator=g).to(torch.bfloat16)   # [(X, q)][p]
+        whole = torch.empty(M * N, dtype=torch.bfloat16, device="cuda")
+        cut = torch.full((M * N,), 3.0, dtype=torch.bfloat16, device="cuda")
+        call(M, N, K, 1, a.data_ptr(), K, 1, 0, b.data_ptr(), 1, K, 0, whole.data_ptr(), N, 0)
+        n4 = N // 4
+        for c in range(4):
+            call(M, n4, K, 1, a.data_ptr(), K, 1, 0, b[c * n4 * K:].data_ptr(), 1, K, 0,
+                 cut[c * n4:].data_ptr(), N, 0)
+    else:
+        M, N, K, batch = X, v, v, R
+        a = torch.randn(batch * M * K, device="cuda", generator=g).to(torch.bfloat16)  # [r][X][c]
+        b = torch.randn(batch * N * K, device="cuda", generator=g).to(torch.bfloat16)  # [r][d][c]
+        whole = torch.empty(batch * M * N, dtype=torch.bfloat16, device="cuda")
+        cut = torch.full((batch * M * N,), 3.0, dtype=torch.bfloat16, device="cuda")
+        call(M, N, K, batch, a.data_ptr(), K, 1, M * K, b.data_ptr(), 1, K, N * K,
+             whole.data_ptr(), N, M * N)
+        b4 = batch // 4
+        for c in range(4):
+            call(M, N, K, b4, a[c * b4 * M * K:].data_ptr(), K, 1, M * K, b[c * b4 * N * K:].data_ptr(),
+                 1, K, N * K, cut[c * b4 * M * N:].data_ptr(), N, M * N)
+    torch.cuda.synchronize()
+    assert torch.isfinite(whole.float()).all()
+    assert torch.equal(whole.view(torch.int16), cut.view(torch.int16))
+
+
 @pytest.mark.parametrize("R,n", [(1, 3), (17, 5), (64, 64), (65, 7), (300, 130), (1024, 256),
                                  (2048, 32)])
 def test_spd_inverse_solve(env, R, n):
