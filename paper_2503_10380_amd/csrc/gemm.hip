@@ -451,235 +451,241 @@ void gemm_bf16_kernel(const KArgs a) {
   using T8 = F8Tile<BN, BBK>;
   uint4 ra[TA::C], rb[B8 ? 1 : TB::C];
   typename T8::Regs r8;
-  // The short-slice path issues the loads of the next tile's first slice
-  // before its epilogue, so they are in flight while the results are stored.
-  constexpr bool DEEP =
-      !B8 && (BBK == BBK_LONG || (FAST && (WGM == 4 || !four_waves<AK, BKC, B8, FAST, OutT>())));
-  constexpr bool CHAIN = FAST && WGM == 2 && !DEEP && !B8;
-  bool primed = false;  // ra, rb hold the first slice of the current tile
-  Coords tc = tile_coords32(blockIdx.x, ntile, a);
-  for (uint32_t vt = blockIdx.x; vt < ntile; vt += gridDim.x) {
-  // lane-dependent addresses are recomputed per tile rather than held in
-  // registers across the tile loop
-  int tid = tid0;
-  if constexpr (CHAIN) asm volatile("" : "+v"(tid));
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const uint32_t vnext = vt + gridDim.x;
-  const bool more = CHAIN && vnext < ntile;
-  const Coords tn = more ? tile_coords32(vnext, ntile, a) : tc;
-  const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
-  const int64_t kbeg = (int64_t)tc.split * a.kchunk;
-  const int64_t kend = min(a.K, kbeg + a.kchunk);
-  const bf16_t* A = (const bf16_t*)a.A + tc.b * a.sab;
-  const bf16_t* B = (const bf16_t*)a.B + tc.b * a.sbb;
-
-  if constexpr (B8) T8::init_scales(r8, a, n0, a.N, tid);
-  f4_t acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
-
-  const int64_t nk = kend > kbeg ? (kend - kbeg + BBK - 1) / BBK : 0;
-  if (nk > 0) {
-    if (!primed) {
-      TA::template load<FAST>(ra, A, sa_row, sa_k, m0, a.M, kbeg, kend, vec, tid);
-      if constexpr (B8) T8::template load<FAST>(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, kbeg, kend, vec, a, tid);
-      else TB::template load<FAST>(rb, B, sb_row, sb_k, n0, a.N, kbeg, kend, vec, tid);
-    }
-    TA::store(ra, As, tid);
-    if constexpr (B8) T8::store(r8, Bs, tid);
-    else TB::store(rb, Bs, tid);
-  }
-  primed = false;
   // A second register stage keeps the global loads of slice k + 2 in flight
   // while slice k is multiplied: for long K slices (two work-groups per CU),
   // and on the unchecked path where it costs no occupancy (256-row tiles, and
   // 128 x 128 tiles already at three waves per SIMD).  Measured on MI355X, it
   // costs more than it gains where it would take a fourth wave away.
-  auto mma = [&](const bf16_t* Ac, const bf16_t* Bc) {
-#pragma unroll
-    for (int ks = 0; ks < BBK; ks += 32) {
-      bf16x8_t af[TM], bfr[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) af[i] = TA::frag(Ac, wm * WM + i * 16, ks, lane);
-#pragma unroll
-      for (int j = 0; j < TN; ++j) bfr[j] = TB::frag(Bc, wn * WN + j * 16, ks, lane);
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
-    }
-  };
-  if constexpr (DEEP) {
-    uint4 ra2[TA::C], rb2[TB::C];
-    // With unchecked loads the slice index is clamped instead of the loads
-    // being skipped past the end (a repeated last slice is never stored):
-    // loads issued on every path let the compiler wait for one stage only.
-    if (FAST || nk > 1) {
-      const int64_t k1 = kbeg + (FAST ? min((int64_t)1, nk - 1) : 1) * BBK;
-      TA::template load<FAST>(ra2, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
-      TB::template load<FAST>(rb2, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
-    }
-    __syncthreads();
-    // slice kt sits in LDS buffer kt % 2; register stage kt % 2 is free and
-    // receives slice kt + 2; stage (kt + 1) % 2 holds slice kt + 1
-    auto step = [&](int64_t kt, uint4 (&la)[TA::C], uint4 (&lb)[TB::C], uint4 (&sa)[TA::C],
-                    uint4 (&sb)[TB::C]) {
-      const int cur = (int)(kt & 1);
-      if (FAST || kt + 2 < nk) {
-        const int64_t k2 = kbeg + (FAST ? min(kt + 2, nk - 1) : kt + 2) * BBK;
-        TA::template load<FAST>(la, A, sa_row, sa_k, m0, a.M, k2, kend, vec, tid);
-        TB::template load<FAST>(lb, B, sb_row, sb_k, n0, a.N, k2, kend, vec, tid);
+  constexpr bool DEEP =
+      !B8 && (BBK == BBK_LONG || (FAST && (WGM == 4 || !four_waves<AK, BKC, B8, FAST, OutT>())));
+  // Chained tiles (unchecked single-stage path only): the loads of the next
+  // tile's first slice are issued before this tile's epilogue, so they are in
+  // flight while its results are stored.
+  constexpr bool CHAIN = FAST && WGM == 2 && !DEEP && !B8;
+  bool primed = false;  // ra, rb hold the first slice of the current tile
+  Coords tc = tile_coords32(blockIdx.x, ntile, a);
+  for (uint32_t vt = blockIdx.x; vt < ntile; vt += gridDim.x) {
+    // lane-dependent addresses are recomputed per tile rather than held in
+    // registers across the tile loop
+    int tid = tid0;
+    if constexpr (CHAIN) asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const uint32_t vnext = vt + gridDim.x;
+    const bool more = CHAIN && vnext < ntile;
+    const Coords tn = more ? tile_coords32(vnext, ntile, a) : tc;
+    const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
+    const int64_t kbeg = (int64_t)tc.split * a.kchunk;
+    const int64_t kend = min(a.K, kbeg + a.kchunk);
+    const bf16_t* A = (const bf16_t*)a.A + tc.b * a.sab;
+    const bf16_t* B = (const bf16_t*)a.B + tc.b * a.sbb;
+
+    if constexpr (B8) T8::init_scales(r8, a, n0, a.N, tid);
+    f4_t acc[TM][TN];
+  #pragma unroll
+    for (int i = 0; i < TM; ++i)
+  #pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int64_t nk = kend > kbeg ? (kend - kbeg + BBK - 1) / BBK : 0;
+    if (nk > 0) {
+      if (!primed) {
+        TA::template load<FAST>(ra, A, sa_row, sa_k, m0, a.M, kbeg, kend, vec, tid);
+        if constexpr (B8)
+          T8::template load<FAST>(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, kbeg, kend,
+                                  vec, a, tid);
+        else TB::template load<FAST>(rb, B, sb_row, sb_k, n0, a.N, kbeg, kend, vec, tid);
       }
-      mma(As + cur * AS, Bs + cur * BS);
-      if (kt + 1 < nk) {
-        TA::store(sa, As + (cur ^ 1) * AS, tid);
-        TB::store(sb, Bs + (cur ^ 1) * BS, tid);
+      TA::store(ra, As, tid);
+      if constexpr (B8) T8::store(r8, Bs, tid);
+      else TB::store(rb, Bs, tid);
+    }
+    primed = false;
+    auto mma = [&](const bf16_t* Ac, const bf16_t* Bc) {
+  #pragma unroll
+      for (int ks = 0; ks < BBK; ks += 32) {
+        bf16x8_t af[TM], bfr[TN];
+  #pragma unroll
+        for (int i = 0; i < TM; ++i) af[i] = TA::frag(Ac, wm * WM + i * 16, ks, lane);
+  #pragma unroll
+        for (int j = 0; j < TN; ++j) bfr[j] = TB::frag(Bc, wn * WN + j * 16, ks, lane);
+  #pragma unroll
+        for (int i = 0; i < TM; ++i)
+  #pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+      }
+    };
+    if constexpr (DEEP) {
+      uint4 ra2[TA::C], rb2[TB::C];
+      // With unchecked loads the slice index is clamped instead of the loads
+      // being skipped past the end (a repeated last slice is never stored):
+      // loads issued on every path let the compiler wait for one stage only.
+      if (FAST || nk > 1) {
+        const int64_t k1 = kbeg + (FAST ? min((int64_t)1, nk - 1) : 1) * BBK;
+        TA::template load<FAST>(ra2, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
+        TB::template load<FAST>(rb2, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
       }
       __syncthreads();
-    };
-    // Both steps run on every trip, so the loads in flight at the top of a
-    // trip are always those into the second stage: the compiler then does not
-    // wait for them before issuing the first stage's loads (a loop that could
-    // come back after one step made it wait for every load in flight).
-    int64_t kt = 0;
-    for (; kt + 1 < nk; kt += 2) {
-      step(kt, ra, rb, ra2, rb2);
-      step(kt + 1, ra2, rb2, ra, rb);
-    }
-    if (kt < nk) step(kt, ra, rb, ra2, rb2);
-  } else {
-  __syncthreads();
-  // the next tile's first slice, loaded during this tile's last slice
-  const int64_t nkbeg = (int64_t)tn.split * a.kchunk;
-  const int64_t nkend = min(a.K, nkbeg + a.kchunk);
-  const bool chain = CHAIN && more && nkend > nkbeg;
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt & 1);
-    const bf16_t* Ac = As + cur * AS;
-    const bf16_t* Bc = Bs + cur * BS;
-    if (kt + 1 < nk) {
-      const int64_t k1 = kbeg + (kt + 1) * BBK;
-      TA::template load<FAST>(ra, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
-      if constexpr (B8) T8::template load<FAST>(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, k1, kend, vec, a, tid);
-      else TB::template load<FAST>(rb, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
-    }
-    mma(Ac, Bc);
-    if (kt + 1 < nk) {
-      TA::store(ra, As + (cur ^ 1) * AS, tid);
-      if constexpr (B8) T8::store(r8, Bs + (cur ^ 1) * BS, tid);
-      else TB::store(rb, Bs + (cur ^ 1) * BS, tid);
-    }
-    __syncthreads();
-  }
-  if constexpr (CHAIN) {
-    if (chain) {
-      TA::template load<FAST>(ra, (const bf16_t*)a.A + tn.b * a.sab, sa_row, sa_k, tn.tm * BM, a.M,
-                              nkbeg, nkend, vec, tid);
-      TB::template load<FAST>(rb, (const bf16_t*)a.B + tn.b * a.sbb, sb_row, sb_k, tn.tn * BN, a.N,
-                              nkbeg, nkend, vec, tid);
-      primed = true;
-    }
-  }
-  }
-
-  // The products are formed as C^T = B^T A^T (B fragment first): element (m, n)
-  // of a 16 x 16 block is register n % 4 of lane m + 16 (n / 4), so each lane
-  // holds four consecutive columns of one row.
-  if constexpr (STAGE) {
-    // Stage the tile through LDS (the K-loop buffers are free after the last
-    // barrier) and write whole 16-byte row chunks.
-    const bool part = a.splits > 1;
-    const int lr = lane & 15, lc = 4 * (lane >> 4);
-    if (!part && sizeof(OutT) == 2) {
-      bf16_t* Cs = (bf16_t*)smem;
-      const float alpha = (float)a.alpha;
-      constexpr int EPC = 8, CPR = BN / EPC, PROWS = 2 * WM;
-      bf16_t* dst = (bf16_t*)a.C + tc.b * a.scb;
-#pragma unroll
-      for (int pass = 0; pass < WGM / 2; ++pass) {
-        if (pass > 0) __syncthreads();
-        if ((wm >> 1) == pass) {
-#pragma unroll
-          for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-              const int lm = (wm & 1) * WM + i * 16 + lr;
-              const int ln = wn * WN + j * 16 + lc;
-              const uint32_t w0 = (uint32_t)f32_to_bf16(alpha * acc[i][j][0]) |
-                                  ((uint32_t)f32_to_bf16(alpha * acc[i][j][1]) << 16);
-              const uint32_t w1 = (uint32_t)f32_to_bf16(alpha * acc[i][j][2]) |
-                                  ((uint32_t)f32_to_bf16(alpha * acc[i][j][3]) << 16);
-              *(uint2*)&Cs[lm * LDC2 + ln] = make_uint2(w0, w1);
-            }
+      // slice kt sits in LDS buffer kt % 2; register stage kt % 2 is free and
+      // receives slice kt + 2; stage (kt + 1) % 2 holds slice kt + 1
+      auto step = [&](int64_t kt, uint4 (&la)[TA::C], uint4 (&lb)[TB::C], uint4 (&sa)[TA::C],
+                      uint4 (&sb)[TB::C]) {
+        const int cur = (int)(kt & 1);
+        if (FAST || kt + 2 < nk) {
+          const int64_t k2 = kbeg + (FAST ? min(kt + 2, nk - 1) : kt + 2) * BBK;
+          TA::template load<FAST>(la, A, sa_row, sa_k, m0, a.M, k2, kend, vec, tid);
+          TB::template load<FAST>(lb, B, sb_row, sb_k, n0, a.N, k2, kend, vec, tid);
+        }
+        mma(As + cur * AS, Bs + cur * BS);
+        if (kt + 1 < nk) {
+          TA::store(sa, As + (cur ^ 1) * AS, tid);
+          TB::store(sb, Bs + (cur ^ 1) * BS, tid);
         }
         __syncthreads();
-        for (int c = tid; c < PROWS * CPR; c += NT) {
-          const int row = c / CPR, col = (c % CPR) * EPC;
-          const int64_t gm = m0 + pass * PROWS + row, gn = n0 + col;
-          if (gm >= a.M) continue;
-          if (a.cvec_ok && gn + EPC <= a.N) {
-            *(uint4*)(dst + gm * a.scm + gn) = *(const uint4*)(Cs + row * LDC2 + col);
-          } else {
-            for (int q = 0; q < EPC; ++q)
-              if (gn + q < a.N) dst[gm * a.scm + gn + q] = Cs[row * LDC2 + col + q];
+      };
+      // Both steps run on every trip, so the loads in flight at the top of a
+      // trip are always those into the second stage: the compiler then does not
+      // wait for them before issuing the first stage's loads (a loop that could
+      // come back after one step made it wait for every load in flight).
+      int64_t kt = 0;
+      for (; kt + 1 < nk; kt += 2) {
+        step(kt, ra, rb, ra2, rb2);
+        step(kt + 1, ra2, rb2, ra, rb);
+      }
+      if (kt < nk) step(kt, ra, rb, ra2, rb2);
+    } else {
+      __syncthreads();
+      // the next tile's first slice, loaded after this tile's last one and
+      // before its epilogue
+      const int64_t nkbeg = (int64_t)tn.split * a.kchunk;
+      const int64_t nkend = min(a.K, nkbeg + a.kchunk);
+      const bool chain = CHAIN && more && nkend > nkbeg;
+      for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        const bf16_t* Ac = As + cur * AS;
+        const bf16_t* Bc = Bs + cur * BS;
+        if (kt + 1 < nk) {
+          const int64_t k1 = kbeg + (kt + 1) * BBK;
+          TA::template load<FAST>(ra, A, sa_row, sa_k, m0, a.M, k1, kend, vec, tid);
+          if constexpr (B8)
+            T8::template load<FAST>(r8, (const uint8_t*)a.B + tc.b * a.sbb, a.sbn, n0, a.N, k1, kend,
+                                    vec, a, tid);
+          else TB::template load<FAST>(rb, B, sb_row, sb_k, n0, a.N, k1, kend, vec, tid);
+        }
+        mma(Ac, Bc);
+        if (kt + 1 < nk) {
+          TA::store(ra, As + (cur ^ 1) * AS, tid);
+          if constexpr (B8) T8::store(r8, Bs + (cur ^ 1) * BS, tid);
+          else TB::store(rb, Bs + (cur ^ 1) * BS, tid);
+        }
+        __syncthreads();
+      }
+      if constexpr (CHAIN) {
+        if (chain) {
+          TA::template load<FAST>(ra, (const bf16_t*)a.A + tn.b * a.sab, sa_row, sa_k, tn.tm * BM, a.M,
+                                  nkbeg, nkend, vec, tid);
+          TB::template load<FAST>(rb, (const bf16_t*)a.B + tn.b * a.sbb, sb_row, sb_k, tn.tn * BN, a.N,
+                                  nkbeg, nkend, vec, tid);
+          primed = true;
+        }
+      }
+    }
+
+    // The products are formed as C^T = B^T A^T (B fragment first): element (m, n)
+    // of a 16 x 16 block is register n % 4 of lane m + 16 (n / 4), so each lane
+    // holds four consecutive columns of one row.
+    if constexpr (STAGE) {
+      // Stage the tile through LDS (the K-loop buffers are free after the last
+      // barrier) and write whole 16-byte row chunks.
+      const bool part = a.splits > 1;
+      const int lr = lane & 15, lc = 4 * (lane >> 4);
+      if (!part && sizeof(OutT) == 2) {
+        bf16_t* Cs = (bf16_t*)smem;
+        const float alpha = (float)a.alpha;
+        constexpr int EPC = 8, CPR = BN / EPC, PROWS = 2 * WM;
+        bf16_t* dst = (bf16_t*)a.C + tc.b * a.scb;
+  #pragma unroll
+        for (int pass = 0; pass < WGM / 2; ++pass) {
+          if (pass > 0) __syncthreads();
+          if ((wm >> 1) == pass) {
+  #pragma unroll
+            for (int i = 0; i < TM; ++i)
+  #pragma unroll
+              for (int j = 0; j < TN; ++j) {
+                const int lm = (wm & 1) * WM + i * 16 + lr;
+                const int ln = wn * WN + j * 16 + lc;
+                const uint32_t w0 = (uint32_t)f32_to_bf16(alpha * acc[i][j][0]) |
+                                    ((uint32_t)f32_to_bf16(alpha * acc[i][j][1]) << 16);
+                const uint32_t w1 = (uint32_t)f32_to_bf16(alpha * acc[i][j][2]) |
+                                    ((uint32_t)f32_to_bf16(alpha * acc[i][j][3]) << 16);
+                *(uint2*)&Cs[lm * LDC2 + ln] = make_uint2(w0, w1);
+              }
           }
+          __syncthreads();
+          for (int c = tid; c < PROWS * CPR; c += NT) {
+            const int row = c / CPR, col = (c % CPR) * EPC;
+            const int64_t gm = m0 + pass * PROWS + row, gn = n0 + col;
+            if (gm >= a.M) continue;
+            if (a.cvec_ok && gn + EPC <= a.N) {
+              *(uint4*)(dst + gm * a.scm + gn) = *(const uint4*)(Cs + row * LDC2 + col);
+            } else {
+              for (int q = 0; q < EPC; ++q)
+                if (gn + q < a.N) dst[gm * a.scm + gn + q] = Cs[row * LDC2 + col + q];
+            }
+          }
+        }
+      } else {
+        // FP32 results: split-K partials (row stride N, alpha applied later) or C
+        float* Cs = (float*)smem;
+        const float alpha = part ? 1.0f : (float)a.alpha;
+        float* dst = part ? (float*)a.partial + ((int64_t)tc.split * a.batch + tc.b) * a.M * a.N
+                          : (float*)a.C + tc.b * a.scb;
+        const int64_t ldd = part ? a.N : a.scm;
+        constexpr int EPC = 4, CPR = BN / EPC;
+  #pragma unroll
+        for (int pass = 0; pass < WGM; ++pass) {
+          if (wm == pass) {
+  #pragma unroll
+            for (int i = 0; i < TM; ++i)
+  #pragma unroll
+              for (int j = 0; j < TN; ++j) {
+                const int lm = i * 16 + lr;
+                const int ln = wn * WN + j * 16 + lc;
+                *(f4_t*)&Cs[lm * LDC4 + ln] = alpha * acc[i][j];
+              }
+          }
+          __syncthreads();
+          for (int c = tid; c < WM * CPR; c += NT) {
+            const int row = c / CPR, col = (c % CPR) * EPC;
+            const int64_t gm = m0 + pass * WM + row, gn = n0 + col;
+            if (gm >= a.M) continue;
+            if (a.cvec_ok && gn + EPC <= a.N) {
+              *(uint4*)(dst + gm * ldd + gn) = *(const uint4*)(Cs + row * LDC4 + col);
+            } else {
+              for (int q = 0; q < EPC; ++q)
+                if (gn + q < a.N) dst[gm * ldd + gn + q] = Cs[row * LDC4 + col + q];
+            }
+          }
+          __syncthreads();
         }
       }
     } else {
-      // FP32 results: split-K partials (row stride N, alpha applied later) or C
-      float* Cs = (float*)smem;
-      const float alpha = part ? 1.0f : (float)a.alpha;
-      float* dst = part ? (float*)a.partial + ((int64_t)tc.split * a.batch + tc.b) * a.M * a.N
-                        : (float*)a.C + tc.b * a.scb;
-      const int64_t ldd = part ? a.N : a.scm;
-      constexpr int EPC = 4, CPR = BN / EPC;
-#pragma unroll
-      for (int pass = 0; pass < WGM; ++pass) {
-        if (wm == pass) {
-#pragma unroll
-          for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-              const int lm = i * 16 + lr;
-              const int ln = wn * WN + j * 16 + lc;
-              *(f4_t*)&Cs[lm * LDC4 + ln] = alpha * acc[i][j];
-            }
-        }
-        __syncthreads();
-        for (int c = tid; c < WM * CPR; c += NT) {
-          const int row = c / CPR, col = (c % CPR) * EPC;
-          const int64_t gm = m0 + pass * WM + row, gn = n0 + col;
-          if (gm >= a.M) continue;
-          if (a.cvec_ok && gn + EPC <= a.N) {
-            *(uint4*)(dst + gm * ldd + gn) = *(const uint4*)(Cs + row * LDC4 + col);
-          } else {
-            for (int q = 0; q < EPC; ++q)
-              if (gn + q < a.N) dst[gm * ldd + gn + q] = Cs[row * LDC4 + col + q];
+  #pragma unroll
+      for (int i = 0; i < TM; ++i)
+  #pragma unroll
+        for (int j = 0; j < TN; ++j)
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t gm = m0 + wm * WM + i * 16 + (lane & 15);
+            const int64_t gn = n0 + wn * WN + j * 16 + 4 * (lane >> 4) + r;
+            if (gm < a.M && gn < a.N) store_out<OutT>(a, tc, gm, gn, (double)acc[i][j][r]);
           }
-        }
-        __syncthreads();
-      }
     }
-  } else {
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t gm = m0 + wm * WM + i * 16 + (lane & 15);
-          const int64_t gn = n0 + wn * WN + j * 16 + 4 * (lane >> 4) + r;
-          if (gm < a.M && gn < a.N) store_out<OutT>(a, tc, gm, gn, (double)acc[i][j][r]);
-        }
-  }
-  if constexpr (!CHAIN) break;
-  // the epilogue's LDS reads end before the next tile's first slice is stored
-  if (more) __syncthreads();
-  tc = tn;
+    if constexpr (!CHAIN) break;
+    // the epilogue's LDS reads end before the next tile's first slice is stored
+    if (more) __syncthreads();
+    tc = tn;
   }
 }
 
