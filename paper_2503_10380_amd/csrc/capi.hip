@@ -471,9 +471,19 @@ int read_status(cpppl_ctx* c) {
   return c->host_status[0];
 }
 
-// -W_m^{-1}, W_m = *_{k != m} Gram_k, on stream `st` into c->inv.  careful:
-// synchronise and retry with a ridge shift while a pivot fails.  Returns retries.
-int prepare_inverse(cpppl_ctx* c, int m, hipStream_t st, bool careful) {
+// Waits for an inverse forked ahead for the next sweep, before the inverse
+// buffers are used for anything else.
+void drop_early_fork(cpppl_ctx* c) {
+  if (!c->alpha_forked) return;
+  CPPPL_HIP(hipStreamSynchronize(c->side));
+  c->alpha_forked = false;
+}
+
+// -W_m^{-1}, W_m = *_{k != m} Gram_k, on stream `st` into c->inv; a failed
+// pivot sets status word `word`.  careful: synchronise and retry with a ridge
+// shift while a pivot fails.  Returns retries.
+int prepare_inverse(cpppl_ctx* c, int m, hipStream_t st, bool careful, int word = 0) {
+  drop_early_fork(c);
   Span sp(c, CPPPL_T_INV, st);
   const int64_t R = c->d.rank;
   const Plan& p = c->plan;
@@ -487,7 +497,7 @@ int prepare_inverse(cpppl_ctx* c, int m, hipStream_t st, bool careful) {
     if (attempt > 0) add_ridge(c->at<double>(p.invA), R, 1e-14 * std::pow(100.0, attempt - 1), st);
     if (careful) zero_ints(c->at<int>(p.status), 1, st);
     c->inv = spd_inverse_neg(c->at<double>(p.invA), c->at<double>(p.invB), c->at<double>(p.invD), R,
-                             c->at<int>(p.status), st);
+                             c->at<int>(p.status) + word, st);
     if (!careful) break;
     CPPPL_HIP(hipStreamSynchronize(st));
     if (read_status(c) == 0) break;
@@ -536,9 +546,9 @@ int solve_mode(cpppl_ctx* c, int m, bool careful) {
 void mark_fork(cpppl_ctx* c) { CPPPL_HIP(hipEventRecord(c->ev_main, c->stream)); }
 
 // Start -W_m^{-1} on the side stream from the point marked by mark_fork.
-void fork_inverse(cpppl_ctx* c, int m) {
+void fork_inverse(cpppl_ctx* c, int m, int word = 0) {
   CPPPL_HIP(hipStreamWaitEvent(c->side, c->ev_main, 0));
-  prepare_inverse(c, m, c->side, false);
+  prepare_inverse(c, m, c->side, false, word);
   CPPPL_HIP(hipEventRecord(c->ev_side, c->side));
 }
 void join_inverse(cpppl_ctx* c) { CPPPL_HIP(hipStreamWaitEvent(c->stream, c->ev_side, 0)); }
@@ -657,11 +667,15 @@ void cp2_current(cpppl_ctx* c, double* out) {
 
 // One ALS sweep on path P; returns ridge retries.  Outside careful mode the
 // inverse of W for alpha, beta and gamma runs on the side stream while the
-// main stream evaluates that factor's MTTKRP.
-int sweep(cpppl_ctx* c, const Path& P, bool careful) {
+// main stream evaluates that factor's MTTKRP.  early_word >= 0: once rho is
+// updated, W_alpha of the next sweep is final, and its inverse is forked on
+// the side stream at once (a failed pivot sets status word early_word), to
+// run beside this sweep's fit and the next sweep's first products.
+int sweep(cpppl_ctx* c, const Path& P, bool careful, int early_word = -1) {
   const Plan& p = c->plan;
   int retries = 0;
   if (c->planted || careful) {
+    drop_early_fork(c);
     if (c->planted) {
       for (int m : {2, 3, 0, 1}) {
         planted_mttkrp(c, m);
@@ -697,11 +711,13 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful) {
       explicit Chunked(cpppl_ctx* x) : c(x) { c->launch_chunks = 4; }
       ~Chunked() { c->launch_chunks = 1; }
     } chunked(c);
-    mark_fork(c);
+    const bool pre = c->alpha_forked;  // W_alpha^{-1} already queued by the previous sweep
+    c->alpha_forked = false;
+    if (!pre) mark_fork(c);
     compute_tau(c, P);
     if (!c->ybeta_valid || c->ybeta_dt != P.dt) compute_Y(c, P, 3, p.Yb);
     compute_Z(c, P, 2);
-    fork_inverse(c, 2);
+    if (!pre) fork_inverse(c, 2);
     compute_M(c, P, 2);
     join_inverse(c);
     apply_inverse(c, 2);
@@ -724,6 +740,12 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful) {
     apply_inverse(c, 0);
     compute_occ(c, 1);
     solve_mode(c, 1, false);
+    if (early_word >= 0) {
+      zero_ints(c->at<int>(p.status) + early_word, 1, c->stream);
+      mark_fork(c);
+      fork_inverse(c, 2, early_word);
+      c->alpha_forked = true;
+    }
   }
   {
     Span sp(c, CPPPL_T_FIT);
@@ -1391,6 +1413,7 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
   const DType main_dt = c->prec != CPPPL_FP64 ? DType::BF16 : DType::F64;
   const int total = opts->max_sweeps + (c->prec != CPPPL_FP64 ? opts->refine_fp64_sweeps : 0);
   double prev_fit = std::numeric_limits<double>::quiet_NaN();
+  drop_early_fork(c);
   sync(c);
   const auto t_start = std::chrono::steady_clock::now();
   auto t_prev = t_start;
@@ -1408,13 +1431,19 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
   auto path_of = [&](int s) { return path_for(c, s >= opts->max_sweeps ? DType::F64 : main_dt); };
   const size_t slot_bytes = S_COUNT * 8 + 16 * sizeof(int);
   auto host_slot = [&](int k) { return c->host_scal + (size_t)k * (S_COUNT + 8); };
+  // Status words 2 and 3 (by sweep parity) flag a failed pivot in an alpha
+  // inverse forked during the previous sweep; alpha_word[slot] names the one
+  // that belongs to the sweep in that slot (-1: none).
+  int alpha_word[2] = {-1, -1};
   // sweep s with its snapshot in the other slot; its scalars and status go to
   // that slot's host buffer, marked by ev_done[slot]
   auto issue = [&](int s) {
     const int slot = c->snap ^ 1;
+    alpha_word[slot] = c->alpha_forked ? 2 + (s & 1) : -1;
     snapshot(c, slot);
     zero_ints(c->at<int>(p.status), 1, c->stream);
-    (void)sweep(c, path_of(s), false);
+    const int early = ahead && !c->planted && next_of(s + 1) >= 0 ? 2 + ((s + 1) & 1) : -1;
+    (void)sweep(c, path_of(s), false, early);
     if (opts->near_cache)
       copy_factor_set(c, p.nearRing + (size_t)(rep->sweeps_done % 6) * factor_set_bytes(c), true);
     CPPPL_HIP(hipMemcpyAsync(host_slot(slot), c->at(p.scal), slot_bytes, hipMemcpyDeviceToHost,
@@ -1430,7 +1459,8 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
     CPPPL_HIP(hipEventSynchronize(c->ev_done[cur_slot]));
     double* hs = host_slot(cur_slot);
     int retries = 0;
-    if (((const int*)(hs + S_COUNT))[0]) {
+    const int* hst = (const int*)(hs + S_COUNT);
+    if (hst[0] || (alpha_word[cur_slot] >= 0 && hst[alpha_word[cur_slot]])) {
       // a Cholesky pivot failed: drop the sweep issued after this one and redo
       // this sweep from its snapshot with ridge retries
       sync(c);
@@ -1482,6 +1512,7 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
       // the sweep issued ahead is past a stop: back to the state after this
       // sweep (factors from the next snapshot, scalars from this readback)
       sync(c);
+      c->alpha_forked = false;  // forked from the state being rolled back
       restore_snapshot(c, nxt_slot);
       CPPPL_HIP(hipMemcpyAsync(c->at(p.scal), hs, S_COUNT * 8, hipMemcpyHostToDevice, c->stream));
       sync(c);
@@ -1505,6 +1536,7 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
     CPPPL_HIP(hipMemcpyAsync(c->host_scal, c->at(p.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
   }
   sync(c);
+  c->alpha_forked = false;
   rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   if (opts->energy) rep->energy_cp = c->host_scal[S_ENERGY];
   if (c->timing) {

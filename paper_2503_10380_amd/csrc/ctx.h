@@ -97,6 +97,9 @@ struct cpppl_ctx {
   hipEvent_t ev_done[2] = {nullptr, nullptr};  // a sweep's results reached host_scal slot k
   int launch_chunks = 1;  // launches per unsplit BF16 product (more while a side inverse is pending)
   int snap = 0;  // snapshot slot holding the state before the most recently issued sweep
+  // -W_alpha^{-1} of the next sweep is queued on the side stream (forked at the
+  // end of the previous sweep); cleared by that sweep, or by waiting for it
+  bool alpha_forked = false;
   double* inv = nullptr;          // buffer holding -W^{-1} of the last prepared mode
 
   double* host_scal = nullptr;  // pinned, two slots of S_COUNT doubles + 16 status ints
