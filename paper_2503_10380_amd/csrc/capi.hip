@@ -400,12 +400,13 @@ void compute_H(cpppl_ctx* c, const Path& P) {
   run_gemm(c, P, g);
 }
 
-void compute_occ(cpppl_ctx* c, int mode) {
-  Span sp(c, CPPPL_T_SOLVE);
+void compute_occ(cpppl_ctx* c, int mode, hipStream_t st = nullptr) {
+  if (!st) st = c->stream;
+  Span sp(c, CPPPL_T_SOLVE, st);
   const int64_t o = c->d.o, R = c->d.rank;
   const double* other = c->at<double>(c->plan.FT[mode == 0 ? 1 : 0]);
   occ_reduce(c->at<double>(c->plan.HT), other, c->at<double>(c->plan.MT), o, R, mode == 0 ? 0 : 1,
-             c->stream);
+             st);
 }
 
 // MTTKRP of a planted CP tensor via cross Grams.
@@ -738,8 +739,14 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful, int early_word = -1) {
     compute_occ(c, 0);
     join_inverse(c);
     apply_inverse(c, 0);
-    compute_occ(c, 1);
-    solve_mode(c, 1, false);
+    // M_rho (H against the new gamma) on the side stream beside rho's inverse
+    mark_fork(c);
+    CPPPL_HIP(hipStreamWaitEvent(c->side, c->ev_main, 0));
+    compute_occ(c, 1, c->side);
+    CPPPL_HIP(hipEventRecord(c->ev_side, c->side));
+    prepare_inverse(c, 1, c->stream, false);
+    join_inverse(c);
+    apply_inverse(c, 1);
     if (early_word >= 0) {
       zero_ints(c->at<int>(p.status) + early_word, 1, c->stream);
       mark_fork(c);
