@@ -628,7 +628,14 @@ void gemm_bf16_kernel(const KArgs a) {
             const int64_t gm = m0 + pass * PROWS + row, gn = n0 + col;
             if (gm >= a.M) continue;
             if (a.cvec_ok && gn + EPC <= a.N) {
-              *(uint4*)(dst + gm * a.scm + gn) = *(const uint4*)(Cs + row * LDC2 + col);
+              // Non-temporal: BF16 products (Y, Z, G, tau) stream to HBM and are
+              // read back only by a later product.  Measured on MI355X at o = 32,
+              // v = 256, X = 768, R = 1024: Y alone 0.248 -> 0.209 ms, the ALS
+              // sweep +2 %.  (FP32 split-K partials, read back at once by the
+              // reduction, keep ordinary stores: no gain measured there.)
+              typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+              const u32x4 v = *(const u32x4*)(Cs + row * LDC2 + col);
+              __builtin_nontemporal_store(v, (u32x4*)(dst + gm * a.scm + gn));
             } else {
               for (int q = 0; q < EPC; ++q)
                 if (gn + q < a.N) dst[gm * a.scm + gn + q] = Cs[row * LDC2 + col + q];
