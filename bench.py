@@ -164,6 +164,30 @@ def roofline_for(cls, flops, nbytes, launch_ms):
             "avg_launch_ms": launch_ms, "hbm_gbs": nbytes / sec / 1e9}
 
 
+def class_rooflines(rep, flops, nbytes):
+    """Per-launch roofline of every MTTKRP class from an ALS report with timing."""
+    out = {}
+    for k in CLASSES:
+        n = rep["n_class"][k]
+        if not n or rep["ms_class"][k] <= 0:
+            continue
+        nl = LAUNCHES[k]
+        r = roofline_for(k, flops[k] / nl, nbytes[k] / nl, rep["ms_class"][k] / (n * nl))
+        r["launches_per_call"] = nl
+        r["share_of_mttkrp_time"] = rep["ms_class"][k] / sum(rep["ms_class"][c] for c in CLASSES)
+        out[k] = r
+    return out
+
+
+def dominant_class(rep, rooflines, tie=0.05):
+    """The class taking the most time; classes within `tie` (relative) of it
+    count as tied, and of those the one furthest from its roofline is taken,
+    so that a near-tie never hides the weaker kernel."""
+    top = max(rooflines, key=lambda k: rep["ms_class"][k])
+    tied = [k for k in rooflines if rep["ms_class"][k] >= (1 - tie) * rep["ms_class"][top]]
+    return min(tied, key=lambda k: rooflines[k]["frac"])
+
+
 def cpu_baseline(cfg, inp, fs, occ=8):
     """The FP64 oracle on a bounded sample: R for the i, j < occ pairs, then one
     textbook ALS sweep on that sub-tensor.  MTTKRP work is linear in the number
@@ -256,9 +280,82 @@ def time_to_fit(cp, torch, cfg, inp, fs, dev_t, dev_b, args):
             "energy_rel_diff": abs(rm["energy_cp"] - r64["energy_cp"]) / abs(r64["energy_cp"]),
         }
     res["fp64_ms_per_sweep"] = float(np.nanmean(r64["ms_hist"]))
+    # the energy criterion (reading P14): both paths run until E_CP changes by
+    # less than etol per FP64 sweep (capped at --max-sweeps); the mixed path's
+    # BF16 phase stops on the windowed fit floor as above
+    etol = args.energy_tol
+    ctx.set_factors(*state)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rm = ctx.als(args.max_sweeps, stop_rule=1, tol=args.bf16_floor, stop_window=8,
+                 refine=args.max_sweeps, refine_etol=etol, energy=True)
+    t_mixed = time.perf_counter() - t0
+    c64.set_factors(*state)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r64 = c64.als(args.max_sweeps, stop_rule=3, tol=etol, energy=True)
+    t_64 = time.perf_counter() - t0
+    eh64 = r64["energy_hist"]
+    ehm = rm["energy_hist"][rm["sweeps"] - rm["refine_sweeps"]:]
+    res[f"energy_tol_{etol:g}"] = {
+        "fp64": {"sweeps": r64["sweeps"], "wall_s": t_64, "fit": r64["fit"],
+                 "energy": r64["energy_cp"], "last_energy_change": float(abs(eh64[-1] - eh64[-2])),
+                 "capped": r64["sweeps"] >= args.max_sweeps},
+        "mixed": {"bf16_sweeps": rm["sweeps"] - rm["refine_sweeps"],
+                  "fp64_sweeps": rm["refine_sweeps"], "wall_s": t_mixed, "fit": rm["fit"],
+                  "energy": rm["energy_cp"],
+                  "last_energy_change": float(abs(ehm[-1] - ehm[-2])) if len(ehm) > 1 else None,
+                  "capped": rm["refine_sweeps"] >= args.max_sweeps},
+        "speedup": t_64 / t_mixed,
+        "fit_rel_diff": abs(rm["fit"] - r64["fit"]) / abs(r64["fit"]),
+        "energy_abs_diff": abs(rm["energy_cp"] - r64["energy_cp"]),
+        "energy_rel_diff": abs(rm["energy_cp"] - r64["energy_cp"]) / abs(r64["energy_cp"]),
+    }
     c64.close()
     ctx.close()
     return res
+
+
+def workload_leg(cp, torch, cfg, prec, args):
+    """Sweep rate and MTTKRP throughput of one more workload and operand
+    precision (the same protocol as the headline: --warmup sweeps, then
+    --steps timed sweeps from the seeded random factors, then the same number
+    with per-class events)."""
+    inp = synth.make_inputs(cfg)
+    fs = synth.init_factors(cfg)
+    ctx = cp.Context(cfg.o, cfg.v, cfg.nx, cfg.rank, prec)
+    ctx.load_t2(torch.tensor(inp.t, device="cuda"))
+    ctx.load_df(torch.tensor(inp.b_vv, device="cuda"))
+    del inp
+    ctx.norm_r2()
+    ctx.set_factors(*fs)
+    if args.warmup:
+        ctx.als(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.als(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rep = ctx.als(args.steps, timing=True)
+    ctx.close()
+    flops = class_flops(cfg)
+    esz = 8 if prec == "fp64" else 2
+    nbytes = class_bytes(cfg, esz=esz, in_esz={"fp64": 8, "bf16": 2, "fp8": 1}[prec])
+    mt_ms = sum(rep["ms_class"][k] for k in CLASSES)
+    tf = sweep_flops(cfg) * args.steps / (mt_ms * 1e-3) / 1e12
+    peak = PEAK["fp64"] if prec == "fp64" else PEAK["bf16"]
+    per = {}
+    for k in CLASSES:
+        n = rep["n_class"][k]
+        if n and rep["ms_class"][k] > 0:
+            sec = rep["ms_class"][k] * 1e-3 / n
+            per[k] = {"ms_per_call": sec * 1e3, "tflops": flops[k] / sec / 1e12,
+                      "frac_of_dtype_peak": flops[k] / sec / 1e12 / peak,
+                      "gbs": nbytes[k] / sec / 1e9, "frac_of_hbm": nbytes[k] / sec / 1e9 / HBM_PEAK_GBS}
+    return {"workload": cfg.name, "o": cfg.o, "v": cfg.v, "nx": cfg.nx, "rank": cfg.rank,
+            "operands": prec, "sweeps_per_s": args.steps / wall, "ms_per_sweep": wall * 1e3 / args.steps,
+            "mttkrp_tflops": tf, "mttkrp_frac_of_dtype_peak": tf / peak,
+            "dtype_peak_tflops": peak, "per_class": per, "fit": rep["fit"]}
 
 
 def _common_warm_start(cp, torch, cfg, inp, fs, dev_b, args):
@@ -479,9 +576,14 @@ def main():
                     help="cap on the BF16 and on the FP64 sweeps that converge the previous step")
     ap.add_argument("--bf16-floor", type=float, default=1e-6,
                     help="smallest (window-averaged) fit change the BF16 phase waits for")
+    ap.add_argument("--energy-tol", type=float, default=1e-9,
+                    help="time-to-fit energy leg: stop when |E_n - E_{n-1}| < this (Ha)")
     ap.add_argument("--max-sweeps", type=int, default=200,
                     help="cap on the sweeps of each time-to-fit run (and on the refinement)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--legs", default="C2:fp64,C5:bf16,C5:fp8",
+                    help="extra workload:precision legs reported beside the headline "
+                         "('' for none)")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--fp8-floor", type=float, default=1e-4,
                     help="precision ablation: fit-change floor of the FP8 sweeps")
@@ -579,15 +681,12 @@ def main():
                         "note": "W^-1 on the side stream for alpha/beta/gamma (overlapped)"}
     mttkrp_ms = sum(rep["ms_class"][k] for k in CLASSES)
     mttkrp_tflops = sweep_flops(cfg) * args.steps / (mttkrp_ms * 1e-3) / 1e12
-    dom = max(CLASSES, key=lambda k: rep["ms_class"][k])
-    # per launch: a class call of the dominant kernel is LAUNCHES[dom] launches
-    nl = LAUNCHES[dom]
-    d_launch_ms = rep["ms_class"][dom] / (rep["n_class"][dom] * nl)
-    roofline = roofline_for(dom, flops[dom] / nl, nbytes[dom] / nl, d_launch_ms)
-    roofline["launches_per_call"] = nl
+    rooflines = class_rooflines(rep, flops, nbytes)
+    dom = dominant_class(rep, rooflines)
+    roofline = dict(rooflines[dom])
     for k in CLASSES:
         if per_class[k]["ms_per_call"]:
-            r = roofline_for(k, flops[k], nbytes[k], per_class[k]["ms_per_call"])
+            r = rooflines[k]
             per_class[k].update({"bound": r["bound"], "frac": r["frac"],
                                  "gbs": nbytes[k] / (per_class[k]["ms_per_call"] * 1e-3) / 1e9})
 
@@ -600,6 +699,10 @@ def main():
                    "o": cfg.o, "v": cfg.v, "nx": cfg.nx, "rank": cfg.rank,
                    "operands": "bf16", "accumulate": "fp32", "solve": "fp64"},
         "roofline": roofline,
+        "roofline_per_class": {k: {f: r[f] for f in ("bound", "achieved", "unit", "frac",
+                                                     "avg_launch_ms", "share_of_mttkrp_time")}
+                               for k, r in rooflines.items()},
+        "roofline_lowest": min(rooflines, key=lambda k: rooflines[k]["frac"]),
         "mttkrp_tflops": mttkrp_tflops,
         "mttkrp_frac_of_bf16_peak": mttkrp_tflops / PEAK["bf16"],
         "per_class": per_class,
@@ -614,6 +717,18 @@ def main():
         del ctx
         torch.cuda.empty_cache()
         out["time_to_fit"] = time_to_fit(cp, torch, cfg, inp, fs, dev_t, dev_b, args)
+    if args.legs:
+        if "ctx" in locals():
+            ctx.close()
+            del ctx
+        del dev_t, dev_b
+        torch.cuda.empty_cache()
+        out["legs"] = {}
+        for leg in args.legs.split(","):
+            name, prec = leg.split(":")
+            print(f"leg {leg}", file=sys.stderr, flush=True)
+            out["legs"][leg] = workload_leg(cp, torch, synth.CONFIGS[name], prec, args)
+            torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, inp, fs)
     print(json.dumps(out))

@@ -8,8 +8,10 @@
  * is fitted by a rank-R CP model
  *   CP_ijab = sum_r lambda_r gamma_ir rho_jr alpha_ar beta_br   (eq. cp-ppl)
  * with alternating least squares (Section "Optimizing the CP-PPL
- * tensor-network", eq. full_der, the W Gram-Hadamard product and its Cholesky
- * solve).  R is never formed: each factor's MTTKRP is a chain of contractions
+ * tensor-network", eq. full_der and the W Gram-Hadamard product; the paper
+ * solves the normal equations by Cholesky, this library by an explicit FP64
+ * inverse of W from the block sweep (Gauss-Jordan) operator, applied as one
+ * GEMM).  R is never formed: each factor's MTTKRP is a chain of contractions
  * of t and B against the other three factors (eq. distribute, eq. foreachr).
  *
  * Conventions for every call:
@@ -45,12 +47,13 @@ typedef enum {
   CPPPL_E_STATE = -2,       /* call out of order (e.g. ALS before inputs) */
   CPPPL_E_HIP = -3,         /* HIP runtime error; context must be destroyed */
   CPPPL_E_NOMEM = -4,       /* bound workspace too small / host allocation failed */
-  CPPPL_E_NOT_SPD = -5,     /* normal-equation matrix W not SPD after ridge retries */
+  CPPPL_E_NOT_SPD = -5,     /* normal-equation matrix W not SPD (a pivot of its block sweep
+                               inverse <= 0 or not finite) after ridge retries */
   CPPPL_E_NONFINITE = -6,   /* NaN or Inf in inputs or results */
   CPPPL_E_UNSUPPORTED = -7  /* operation not available in this configuration */
 } cpppl_status;
 
-/* Operand precision of the MTTKRP contractions.  Grams, W, the Cholesky solve,
+/* Operand precision of the MTTKRP contractions.  Grams, W, its inverse and the solve,
  * the factor masters, the fit and the energy are FP64 in all of them, and the
  * FP64 masters of t and B are kept for the FP64 refinement sweeps. */
 typedef enum {
@@ -75,7 +78,9 @@ typedef struct {
 typedef struct {
   int max_sweeps;        /* number of ALS sweeps (upper bound when a stop rule is set) */
   int stop_rule;         /* 0: none; 1: |fit_n - fit_{n-1}| < tol (eq. canon);
-                            2: eta < tol (eq. N3_stopping) */
+                            2: eta < tol (eq. N3_stopping);
+                            3: |E_n - E_{n-1}| < tol, E = E_CP after each sweep (the energy
+                               contraction below; with stop_window w, |E_n - E_{n-w}| / w) */
   double tol;
   int refine_fp64_sweeps;/* BF16 contexts: FP64 sweeps appended after the BF16 ones */
   int history_cap;       /* entries available in the report's history arrays */
@@ -92,6 +97,15 @@ typedef struct {
   int near_cache;        /* non-zero: keep the last six iterates; when the call runs n > 5
                             sweeps, the (n-5)th becomes the near-optimal cache used by
                             CPPPL_WS_NEAR_OPTIMAL (otherwise the previous cache stays) */
+  int energy_every;      /* non-zero: evaluate E_CP = sum CP t after every sweep (into the
+                            report's energy_hist; implied by stop_rule 3).  In the sweep
+                            dtype: FP64 sweeps give it in FP64, BF16 / FP8 sweeps from a
+                            bfloat16 tau.  tau' = KR(gamma, rho)^T t of the updated factors
+                            is what the next sweep starts from, so it is formed once and
+                            reused: the cost is O(R v^2) per sweep, not an extra product. */
+  double refine_etol;    /* > 0: the FP64 refinement stops once |E_n - E_{n-1}| < refine_etol
+                            between two FP64 refinement sweeps (E_CP in FP64, at least two
+                            refinement sweeps).  With refine_tol also set, both must hold. */
 } cpppl_als_opts;
 
 /* Kernel classes timed when opts.timing is set (index into ms_class / n_class). */
@@ -102,7 +116,7 @@ enum {
   CPPPL_T_M = 3,       /* M = B . Z, split-K         (S5 / S7) */
   CPPPL_T_G = 4,       /* per-r G = Y_a^T Y_b        (S8) */
   CPPPL_T_H = 5,       /* H = t . G, split-K         (S9) */
-  CPPPL_T_SOLVE = 6,   /* occupied reductions of H, Grams, W, Cholesky, solve, normalise */
+  CPPPL_T_SOLVE = 6,   /* occupied reductions of H, Grams, solve F = M W^-1, normalise */
   CPPPL_T_FIT = 7,     /* fit, eta, energy scalars (S11, S12) */
   CPPPL_T_INV = 8,     /* W and its inverse (side stream for alpha, beta, gamma: overlapped) */
   CPPPL_T_COUNT = 16
@@ -110,7 +124,8 @@ enum {
 
 typedef struct {
   int sweeps_done;       /* sweeps run in this call (including refinement) */
-  int ridge_retries;     /* Cholesky retries with a ridge shift */
+  int ridge_retries;     /* retries of the W inverse with a ridge shift W + delta tr(W)/R I
+                            after a failed pivot (delta = 1e-14 * 100^k, k = 0..4) */
   double fit;            /* 1 - ||R - CP|| / ||R||  (eq. cpfit) after the last sweep */
   double loss;           /* 0.5 ||R - CP||^2 (eq. loss_function) */
   double inner;          /* <R, CP> */
@@ -124,6 +139,11 @@ typedef struct {
   double* eta_hist;      /* caller-owned, history_cap entries, or NULL */
   double* ms_hist;       /* caller-owned, per-sweep milliseconds, or NULL */
   int refine_done;       /* of sweeps_done, the FP64 refinement sweeps */
+  double* energy_hist;   /* caller-owned, history_cap entries, or NULL: E_CP after each sweep
+                            where it was evaluated (opts.energy_every, stop_rule 3, refine_etol),
+                            else NaN */
+  int careful_sweeps;    /* sweeps redone synchronously from their snapshot after a failed
+                            pivot of a W inverse (each then retries with ridge shifts) */
 } cpppl_als_report;
 
 /* ---- lifecycle ----------------------------------------------------------- */
@@ -284,9 +304,12 @@ CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* ctx, const double* dt, int on
  * column, sign-aligned) into the network's training set. */
 CPPPL_API cpppl_status cpppl_ws_training_rows(cpppl_ctx* ctx, cpppl_mlp* mlp);
 
-/* ---- errors ---------------------------------------------------------------- */
+/* ---- errors and build identity --------------------------------------------- */
 CPPPL_API const char* cpppl_last_error(const cpppl_ctx* ctx);
 CPPPL_API const char* cpppl_status_str(cpppl_status s);
+/* SHA-256 (hex) of the HIP sources and headers this library was built from
+ * (static string), so that a caller can refuse a library built from other sources. */
+CPPPL_API const char* cpppl_build_hash(void);
 
 #ifdef __cplusplus
 }

@@ -1,7 +1,7 @@
 /*
  * cpppl_testing.h -- kernel-level test hooks of libcpppl (not part of the
  * product ABI; used by the parity tests to check the matrix-core GEMM and the
- * Cholesky solve in isolation).  All pointers are device pointers on the
+ * block sweep-operator SPD inverse in isolation).  All pointers are device pointers on the
  * current HIP device; work is enqueued on `stream` and the call synchronises it.
  */
 #ifndef CPPPL_TESTING_H
@@ -53,6 +53,16 @@ CPPPL_API cpppl_status cpppl_test_dequant_e4m3(const uint8_t* q, int64_t n, floa
  * 1 bad pivot. */
 CPPPL_API cpppl_status cpppl_test_spd_solve(double* W, int64_t R, const double* X, double* Y,
                                             int64_t n, double* work, int* status, void* stream);
+
+/* Failure-path hook: in the next cpppl_als call on ctx, the W_alpha inverse
+ * that is forked one sweep early for sweep `sweep` (0-based within that call;
+ * forked while the sweep before it runs, only when sweeps are issued ahead)
+ * reports a failed pivot although none failed.  The call then takes its
+ * recovery path: the sweep issued ahead is dropped and that sweep is redone
+ * synchronously from its snapshot under the ridge rule (report.careful_sweeps).
+ * A host-side flag read when the sweep is issued; -1 clears it; cleared at the
+ * end of every cpppl_als call.  E_ARG for a NULL ctx or sweep < -1. */
+CPPPL_API cpppl_status cpppl_test_inject_alpha_fault(cpppl_ctx* ctx, int sweep);
 
 #ifdef __cplusplus
 }

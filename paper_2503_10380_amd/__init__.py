@@ -41,7 +41,8 @@ class AlsOpts(C.Structure):
     _fields_ = [("max_sweeps", C.c_int), ("stop_rule", C.c_int), ("tol", C.c_double),
                 ("refine_fp64_sweeps", C.c_int), ("history_cap", C.c_int), ("energy", C.c_int),
                 ("timing", C.c_int), ("refine_tol", C.c_double), ("stop_window", C.c_int),
-                ("eta", C.c_int), ("near_cache", C.c_int)]
+                ("eta", C.c_int), ("near_cache", C.c_int), ("energy_every", C.c_int),
+                ("refine_etol", C.c_double)]
 
 
 class AlsReport(C.Structure):
@@ -50,7 +51,8 @@ class AlsReport(C.Structure):
                 ("eta", C.c_double), ("energy_cp", C.c_double), ("ms_total", C.c_double),
                 ("ms_class", C.c_double * 16), ("n_class", C.c_int * 16),
                 ("fit_hist", C.POINTER(C.c_double)), ("eta_hist", C.POINTER(C.c_double)),
-                ("ms_hist", C.POINTER(C.c_double)), ("refine_done", C.c_int)]
+                ("ms_hist", C.POINTER(C.c_double)), ("refine_done", C.c_int),
+                ("energy_hist", C.POINTER(C.c_double)), ("careful_sweeps", C.c_int)]
 
 
 _lib = None
@@ -71,6 +73,7 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run `python -m paper_2503_10380_amd.build`")
+    from .build import source_hash
     # One HIP runtime per process: torch ships its own libamdhip64 (same soname
     # as ROCm's).  Importing torch first makes the library bind to that copy, so
     # that torch's streams and device memory are valid handles inside it.
@@ -116,11 +119,17 @@ def load_library(path: str = LIB_PATH):
         "cpppl_ws_training_rows": (st, [_P, _P]),
         "cpppl_last_error": (C.c_char_p, [_P]),
         "cpppl_status_str": (C.c_char_p, [C.c_int]),
+        "cpppl_build_hash": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    built = lib.cpppl_build_hash().decode()
+    want = source_hash()
+    if built != want:
+        raise RuntimeError(f"{path} was built from other sources (hash {built[:16]}, sources "
+                           f"{want[:16]}); rebuild with `python -m paper_2503_10380_amd.build`")
     _lib = lib
     return lib
 
@@ -270,28 +279,41 @@ class Context:
 
     # ------------------------------------------------------------------ work
     def als(self, sweeps, stop_rule=0, tol=0.0, refine=0, energy=False, timing=False,
-            refine_tol=0.0, stop_window=1, eta=False, near_cache=False):
+            refine_tol=0.0, stop_window=1, eta=False, near_cache=False, energy_every=False,
+            refine_etol=0.0):
         cap = sweeps + refine
         opts = AlsOpts(sweeps, stop_rule, tol, refine, cap, int(bool(energy)), int(bool(timing)),
-                       refine_tol, stop_window, int(bool(eta)), int(bool(near_cache)))
+                       refine_tol, stop_window, int(bool(eta)), int(bool(near_cache)),
+                       int(bool(energy_every)), refine_etol)
         fit = np.full(cap, np.nan)
         eta_h = np.full(cap, np.nan)
         ms = np.full(cap, np.nan)
+        en = np.full(cap, np.nan)
         rep = AlsReport()
         rep.fit_hist = fit.ctypes.data_as(_D)
         rep.eta_hist = eta_h.ctypes.data_as(_D)
         rep.ms_hist = ms.ctypes.data_as(_D)
+        rep.energy_hist = en.ctypes.data_as(_D)
         self._call("cpppl_als", C.byref(opts), C.byref(rep))
         n = rep.sweeps_done
         return {
             "sweeps": n, "refine_sweeps": rep.refine_done, "ridge_retries": rep.ridge_retries,
+            "careful_sweeps": rep.careful_sweeps,
             "fit": rep.fit, "loss": rep.loss,
             "inner": rep.inner, "cp_norm2": rep.cp_norm2, "eta": rep.eta,
             "energy_cp": rep.energy_cp, "ms_total": rep.ms_total,
             "ms_class": {k: rep.ms_class[i] for i, k in enumerate(T_CLASSES)},
             "n_class": {k: rep.n_class[i] for i, k in enumerate(T_CLASSES)},
             "fit_hist": fit[:n].copy(), "eta_hist": eta_h[:n].copy(), "ms_hist": ms[:n].copy(),
+            "energy_hist": en[:n].copy(),
         }
+
+    def inject_alpha_fault(self, sweep):
+        """Test hook (cpppl_testing.h): the next als() call sees a failed pivot
+        in the W_alpha inverse forked early for sweep `sweep`."""
+        fn = self.lib.cpppl_test_inject_alpha_fault
+        fn.restype, fn.argtypes = C.c_int, [_P, C.c_int]
+        self._check(fn(self.h, int(sweep)), self.h)
 
     def mttkrp(self, mode, precision=None):
         prec = self.precision if precision is None else PRECISIONS.get(precision, precision)

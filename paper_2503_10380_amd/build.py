@@ -4,6 +4,7 @@
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -25,9 +26,26 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
+def source_hash() -> str:
+    """SHA-256 over every HIP source and header the library is built from
+    (csrc/*.hip, csrc/*.h, include/*.h), names and contents in sorted order.
+    The build embeds it; the binding refuses a library whose hash differs."""
+    files = []
+    for d, exts in ((CSRC, (".hip", ".h")), (INCLUDE, (".h",))):
+        files += [os.path.join(d, f) for f in os.listdir(d) if f.endswith(exts)]
+    h = hashlib.sha256()
+    for path in sorted(files, key=lambda f: os.path.relpath(f, os.path.dirname(HERE))):
+        h.update(os.path.relpath(path, os.path.dirname(HERE)).encode())
+        h.update(b"\0")
+        with open(path, "rb") as f:
+            h.update(f.read())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
+def _compile(src: str, src_hash: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, f'-DCPPPL_SRC_HASH="{src_hash}"', "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -38,8 +56,9 @@ def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
     jobs = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    src_hash = source_hash()
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, src_hash), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -10,7 +10,8 @@
 //   G[r][c][d] = sum_X Y_alpha[r][X][c] Y_beta[r][X][d],  H[r][ij] = sum_cd G[r][cd] t_ijcd
 //   gamma: M[r][i] = sum_j H[r][ij] rho_jr;  rho: M[r][j] = sum_i H[r][ij] gamma_ir
 // then F^T = W^{-1} M^T with W the Hadamard product of the other three Grams,
-// Cholesky-factored in FP64, and the rows of F^T are scaled to unit 2-norm
+// inverted in FP64 by the block sweep (Gauss-Jordan) operator where the paper
+// takes a Cholesky factorisation, and the rows of F^T are scaled to unit 2-norm
 // (the norms are lambda).  Y_beta of the updated beta is kept for the next
 // sweep's alpha update (caching of intermediates across gradient evaluations).
 #include <algorithm>
@@ -21,6 +22,7 @@
 #include <stdexcept>
 #include <string>
 
+#include "../../include/cpppl_testing.h"
 #include "ctx.h"
 #include "linalg.h"
 #include "ops.h"
@@ -546,10 +548,18 @@ int solve_mode(cpppl_ctx* c, int m, bool careful) {
 // Marks the point of the main stream after which the Grams W_m needs are ready.
 void mark_fork(cpppl_ctx* c) { CPPPL_HIP(hipEventRecord(c->ev_main, c->stream)); }
 
+__global__ void set_flag_kernel(int* flag) { *flag = 1; }
+
 // Start -W_m^{-1} on the side stream from the point marked by mark_fork.
-void fork_inverse(cpppl_ctx* c, int m, int word = 0) {
+// fault: the test hook's injected failure, a flag raised after the inverse
+// (before the join event, so the sweep's status readback sees it).
+void fork_inverse(cpppl_ctx* c, int m, int word = 0, bool fault = false) {
   CPPPL_HIP(hipStreamWaitEvent(c->side, c->ev_main, 0));
   prepare_inverse(c, m, c->side, false, word);
+  if (fault) {
+    hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, c->side, c->at<int>(c->plan.status) + word);
+    CPPPL_LAUNCH_CHECK("set_flag");
+  }
   CPPPL_HIP(hipEventRecord(c->ev_side, c->side));
 }
 void join_inverse(cpppl_ctx* c) { CPPPL_HIP(hipStreamWaitEvent(c->stream, c->ev_side, 0)); }
@@ -573,7 +583,7 @@ void mttkrp_into_MT(cpppl_ctx* c, const Path& P, int mode) {
     compute_H(c, P);
     compute_occ(c, mode);
   }
-  c->ybeta_valid = false;
+  c->ybeta_valid = c->tau_valid = false;
 }
 
 // eta terms: nn = cp2 (this sweep), np = lam^T (* F_k^T Fprev_k) lamprev, pp = previous cp2.
@@ -655,7 +665,7 @@ void restore_snapshot(cpppl_ctx* c, int slot) {
     refresh_lowp(c, m);
   }
   copy_d2d(c, p.lam, p.lamprev[slot], (size_t)R * 8);
-  c->ybeta_valid = false;
+  c->ybeta_valid = c->tau_valid = false;
 }
 
 // cp2 of the current factors into sc[S_CP2_PREV] (eta reference for the first sweep).
@@ -675,15 +685,19 @@ void cp2_current(cpppl_ctx* c, double* out) {
 int sweep(cpppl_ctx* c, const Path& P, bool careful, int early_word = -1) {
   const Plan& p = c->plan;
   int retries = 0;
+  // tau of this sweep's gamma and rho, left by the previous sweep's energy
+  bool have_tau = c->tau_valid && c->tau_dt == P.dt;
+  c->tau_valid = false;
   if (c->planted || careful) {
     drop_early_fork(c);
+    have_tau = have_tau && !c->planted;
     if (c->planted) {
       for (int m : {2, 3, 0, 1}) {
         planted_mttkrp(c, m);
         retries += solve_mode(c, m, careful);
       }
     } else {
-      compute_tau(c, P);
+      if (!have_tau) compute_tau(c, P);
       if (!c->ybeta_valid || c->ybeta_dt != P.dt) compute_Y(c, P, 3, p.Yb);
       compute_Z(c, P, 2);
       compute_M(c, P, 2);
@@ -715,7 +729,7 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful, int early_word = -1) {
     const bool pre = c->alpha_forked;  // W_alpha^{-1} already queued by the previous sweep
     c->alpha_forked = false;
     if (!pre) mark_fork(c);
-    compute_tau(c, P);
+    if (!have_tau) compute_tau(c, P);
     if (!c->ybeta_valid || c->ybeta_dt != P.dt) compute_Y(c, P, 3, p.Yb);
     compute_Z(c, P, 2);
     if (!pre) fork_inverse(c, 2);
@@ -750,7 +764,7 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful, int early_word = -1) {
     if (early_word >= 0) {
       zero_ints(c->at<int>(p.status) + early_word, 1, c->stream);
       mark_fork(c);
-      fork_inverse(c, 2, early_word);
+      fork_inverse(c, 2, early_word, c->inject_now);
       c->alpha_forked = true;
     }
   }
@@ -761,6 +775,17 @@ int sweep(cpppl_ctx* c, const Path& P, bool careful, int early_word = -1) {
     fit_scalars(c->at<double>(p.MT), c->at<double>(p.FT[1]), c->d.o, c->at<double>(p.lam), G,
                 c->d.rank, c->at<double>(p.scal) + S_NORM_R2, c->at<double>(p.rowbuf),
                 c->at<double>(p.scal) + S_FIT, c->stream);
+  }
+  if (c->want_energy && !c->planted) {
+    // E_CP at the updated factors: tau' = KR(gamma', rho')^T t is exactly the
+    // tau the next sweep starts from, so it is kept for it (no extra product)
+    compute_tau(c, P);
+    Span sp(c, CPPPL_T_FIT);
+    energy_from_tau(c->at(p.tau), P.dt, c->at<double>(p.FT[2]), c->at<double>(p.FT[3]),
+                    c->at<double>(p.lam), c->d.rank, c->d.v, c->at<double>(p.rowbuf),
+                    c->at<double>(p.scal) + S_ENERGY, c->stream);
+    c->tau_valid = true;
+    c->tau_dt = P.dt;
   }
   if (c->want_eta) {
     compute_eta(c);
@@ -823,7 +848,7 @@ void compute_norm_r2(cpppl_ctx* c) {
                          c->at<double>(p.sums), sc + S_NORM_R2, c->stream);
   }
   c->norm_valid = true;
-  c->ybeta_valid = false;  // the region holding Y_beta was overwritten
+  c->ybeta_valid = c->tau_valid = false;  // the region holding Y_beta was overwritten
 }
 
 void ensure_norm(cpppl_ctx* c) {
@@ -841,6 +866,8 @@ void compute_energy(cpppl_ctx* c, double* out) {
   energy_from_tau(c->at(c->plan.tau), DType::F64, c->at<double>(c->plan.FT[2]),
                   c->at<double>(c->plan.FT[3]), c->at<double>(c->plan.lam), c->d.rank, c->d.v,
                   c->at<double>(c->plan.rowbuf), out, c->stream);
+  c->tau_valid = true;
+  c->tau_dt = DType::F64;
 }
 
 void require_inputs(cpppl_ctx* c) {
@@ -940,7 +967,7 @@ void init_after_factors(cpppl_ctx* c) {
   }
   cp2_current(c, c->at<double>(c->plan.scal) + S_CP2_PREV);
   c->have_factors = true;
-  c->ybeta_valid = false;
+  c->ybeta_valid = c->tau_valid = false;
 }
 
 }  // namespace
@@ -1006,7 +1033,7 @@ void ws_add_dt(cpppl_ctx* c) {
 void ws_derive_t(cpppl_ctx* c) {
   derive_t(c);
   c->norm_valid = false;
-  c->ybeta_valid = false;
+  c->ybeta_valid = c->tau_valid = false;
 }
 void ws_ensure_norm(cpppl_ctx* c) { ensure_norm(c); }
 void ws_copy(cpppl_ctx* c, size_t dst, size_t src, size_t bytes) { copy_d2d(c, dst, src, bytes); }
@@ -1124,7 +1151,7 @@ CPPPL_API cpppl_status cpppl_bind_workspace(cpppl_ctx* c, void* dev_ptr, size_t 
   c->ws = (char*)dev_ptr;
   c->ws_bytes = bytes;
   c->have_t = c->have_b = c->have_factors = c->planted = false;
-  c->norm_valid = c->ybeta_valid = c->ws_valid = false;
+  c->norm_valid = c->ybeta_valid = c->tau_valid = c->ws_valid = false;
   zero_ints(c->at<int>(c->plan.status), 16, c->stream);
   zero_doubles(c->at<double>(c->plan.scal), S_COUNT, c->stream);
   API_CATCH(c)
@@ -1165,7 +1192,7 @@ CPPPL_API cpppl_status cpppl_load_t2(cpppl_ctx* c, const double* t, int on_devic
   c->have_t = true;
   c->planted = false;
   c->norm_valid = false;
-  c->ybeta_valid = false;
+  c->ybeta_valid = c->tau_valid = false;
   API_CATCH(c)
 }
 
@@ -1192,7 +1219,7 @@ CPPPL_API cpppl_status cpppl_load_singles(cpppl_ctx* c, const double* t1, const 
   }
   dress_t(c);
   c->norm_valid = false;
-  c->ybeta_valid = false;
+  c->ybeta_valid = c->tau_valid = false;
   API_CATCH(c)
 }
 
@@ -1209,7 +1236,7 @@ CPPPL_API cpppl_status cpppl_load_df(cpppl_ctx* c, const double* b, int on_devic
   c->have_b = true;
   c->planted = false;
   c->norm_valid = false;
-  c->ybeta_valid = false;
+  c->ybeta_valid = c->tau_valid = false;
   API_CATCH(c)
 }
 
@@ -1236,7 +1263,7 @@ CPPPL_API cpppl_status cpppl_load_planted(cpppl_ctx* c, const double* fi, const 
   c->rank_p = rank_p;
   c->planted = true;
   c->norm_valid = false;
-  c->ybeta_valid = false;
+  c->ybeta_valid = c->tau_valid = false;
   API_CATCH(c)
 }
 
@@ -1370,7 +1397,7 @@ CPPPL_API cpppl_status cpppl_reconstruct(cpppl_ctx* c, double* out, int symmetri
                c->stream, nullptr, c->at<double>(p.lam));
   khatri_rao_t(c->at<double>(p.FT[2]), c->at<double>(p.FT[3]), v, R, c->at(p.big), DType::F64,
                c->stream);
-  c->ybeta_valid = false;
+  c->ybeta_valid = c->tau_valid = false;
   Gemm g;  // CP[ij][ab] = sum_r Kt[r][ij] Ka[r][ab]
   g.M = o * o; g.N = v * v; g.K = R;
   g.A = c->at(p.Kt); g.sam = 1; g.sak = o * o;
@@ -1400,13 +1427,20 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
   API_TRY(c)
   if (!opts || !rep) throw std::invalid_argument("opts/report is NULL");
   if (opts->max_sweeps < 0 || opts->refine_fp64_sweeps < 0) throw std::invalid_argument("negative sweep count");
-  if (opts->stop_rule < 0 || opts->stop_rule > 2) throw std::invalid_argument("stop_rule must be 0, 1 or 2");
+  if (opts->stop_rule < 0 || opts->stop_rule > 3) throw std::invalid_argument("stop_rule must be 0..3");
   if (!(opts->refine_tol >= 0.0)) throw std::invalid_argument("refine_tol must be >= 0");
+  if (!(opts->refine_etol >= 0.0)) throw std::invalid_argument("refine_etol must be >= 0");
   if (opts->stop_window < 0 || opts->stop_window > 64) throw std::invalid_argument("stop_window must be 0..64");
   const int win = opts->stop_window > 1 ? opts->stop_window : 1;
   c->want_eta = opts->eta != 0 || opts->stop_rule == 2;
-  std::vector<double> main_fits;
+  std::vector<double> main_fits, main_energies;
   require_inputs(c);
+  if (c->planted && (opts->stop_rule == 3 || opts->energy_every || opts->refine_etol > 0.0))
+    throw StatusError(CPPPL_E_UNSUPPORTED, "no energy for a planted tensor");
+  // energy every sweep: on request, for the energy stop rule, and in the FP64
+  // refinement when it stops on the energy change
+  const bool energy_main = opts->energy_every != 0 || opts->stop_rule == 3;
+  const bool energy_refine = energy_main || opts->refine_etol > 0.0;
   ensure_norm(c);
   const Plan& p = c->plan;
   c->timing = opts->timing != 0;
@@ -1415,11 +1449,13 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
   rep->sweeps_done = 0;
   rep->refine_done = 0;
   rep->ridge_retries = 0;
+  rep->careful_sweeps = 0;
   rep->energy_cp = std::numeric_limits<double>::quiet_NaN();
   for (int k = 0; k < 16; ++k) { rep->ms_class[k] = 0.0; rep->n_class[k] = 0; }
   const DType main_dt = c->prec != CPPPL_FP64 ? DType::BF16 : DType::F64;
   const int total = opts->max_sweeps + (c->prec != CPPPL_FP64 ? opts->refine_fp64_sweeps : 0);
   double prev_fit = std::numeric_limits<double>::quiet_NaN();
+  double prev_energy = std::numeric_limits<double>::quiet_NaN();
   drop_early_fork(c);
   sync(c);
   const auto t_start = std::chrono::steady_clock::now();
@@ -1450,7 +1486,10 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
     snapshot(c, slot);
     zero_ints(c->at<int>(p.status), 1, c->stream);
     const int early = ahead && !c->planted && next_of(s + 1) >= 0 ? 2 + ((s + 1) & 1) : -1;
+    c->want_energy = s >= opts->max_sweeps ? energy_refine : energy_main;
+    c->inject_now = early >= 0 && s + 1 == c->inject_alpha_fault;
     (void)sweep(c, path_of(s), false, early);
+    c->inject_now = false;
     if (opts->near_cache)
       copy_factor_set(c, p.nearRing + (size_t)(rep->sweeps_done % 6) * factor_set_bytes(c), true);
     CPPPL_HIP(hipMemcpyAsync(host_slot(slot), c->at(p.scal), slot_bytes, hipMemcpyDeviceToHost,
@@ -1468,14 +1507,16 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
     int retries = 0;
     const int* hst = (const int*)(hs + S_COUNT);
     if (hst[0] || (alpha_word[cur_slot] >= 0 && hst[alpha_word[cur_slot]])) {
-      // a Cholesky pivot failed: drop the sweep issued after this one and redo
+      // a pivot of the W inverse failed: drop the sweep issued after this one and redo
       // this sweep from its snapshot with ridge retries
       sync(c);
       nxt = -1;
       restore_snapshot(c, cur_slot);
       CPPPL_HIP(hipMemcpyAsync(c->at<double>(p.scal) + S_CP2_PREV, hs + S_ETA + 2, 8,
                                hipMemcpyHostToDevice, c->stream));
+      c->want_energy = cur >= opts->max_sweeps ? energy_refine : energy_main;
       retries = sweep(c, path_of(cur), true);
+      rep->careful_sweeps++;
       if (opts->near_cache)
         copy_factor_set(c, p.nearRing + (size_t)(rep->sweeps_done % 6) * factor_set_bytes(c), true);
       CPPPL_HIP(hipMemcpyAsync(hs, c->at(p.scal), S_COUNT * 8, hipMemcpyDeviceToHost, c->stream));
@@ -1485,6 +1526,8 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
     rep->ridge_retries += retries;
     const double fit = hs[S_FIT + 3];
     const double eta = c->want_eta ? hs[S_ETA + 3] : std::numeric_limits<double>::quiet_NaN();
+    const bool have_e = cur >= opts->max_sweeps ? energy_refine : energy_main;
+    const double energy = have_e ? hs[S_ENERGY] : std::numeric_limits<double>::quiet_NaN();
     if (!std::isfinite(fit) || !std::isfinite(hs[S_FIT + 1])) {
       sync(c);
       throw StatusError(CPPPL_E_NONFINITE, "non-finite fit after sweep " + std::to_string(cur + 1));
@@ -1495,6 +1538,8 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
     if (rep->fit_hist && rep->sweeps_done < opts->history_cap) rep->fit_hist[rep->sweeps_done] = fit;
     if (rep->eta_hist && rep->sweeps_done < opts->history_cap) rep->eta_hist[rep->sweeps_done] = eta;
     if (rep->ms_hist && rep->sweeps_done < opts->history_cap) rep->ms_hist[rep->sweeps_done] = ms;
+    if (rep->energy_hist && rep->sweeps_done < opts->history_cap)
+      rep->energy_hist[rep->sweeps_done] = energy;
     rep->sweeps_done++;
     if (refining) rep->refine_done++;
     rep->fit = fit;
@@ -1510,10 +1555,22 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
           std::fabs(fit - main_fits[nf - 1 - win]) / win < opts->tol)
         stop_main = true;
       if (opts->stop_rule == 2 && eta < opts->tol) stop_main = true;
-    } else if (opts->refine_tol > 0.0 && std::fabs(fit - prev_fit) < opts->refine_tol) {
-      done = true;
+      main_energies.push_back(energy);
+      const size_t ne = main_energies.size();
+      if (opts->stop_rule == 3 && ne > (size_t)win &&
+          std::fabs(energy - main_energies[ne - 1 - win]) / win < opts->tol)
+        stop_main = true;
+    } else if (opts->refine_tol > 0.0 || opts->refine_etol > 0.0) {
+      // the refinement stops once every criterion that is set holds; the
+      // energy change is taken between two FP64 sweeps (the last main sweep's
+      // energy, if any, came from low-precision operands)
+      const bool fit_ok = opts->refine_tol <= 0.0 || std::fabs(fit - prev_fit) < opts->refine_tol;
+      const bool e_ok = opts->refine_etol <= 0.0 ||
+                        (rep->refine_done >= 2 && std::fabs(energy - prev_energy) < opts->refine_etol);
+      done = fit_ok && e_ok;
     }
     prev_fit = fit;
+    prev_energy = energy;
     const int want = done ? -1 : next_of(cur + 1);
     if (nxt >= 0 && nxt != want) {
       // the sweep issued ahead is past a stop: back to the state after this
@@ -1544,6 +1601,8 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
   }
   sync(c);
   c->alpha_forked = false;
+  c->want_energy = false;
+  c->inject_alpha_fault = -1;
   rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   if (opts->energy) rep->energy_cp = c->host_scal[S_ENERGY];
   if (c->timing) {
@@ -1559,7 +1618,18 @@ CPPPL_API cpppl_status cpppl_als(cpppl_ctx* c, const cpppl_als_opts* opts, cpppl
   API_CATCH(c)
 }
 
+CPPPL_API cpppl_status cpppl_test_inject_alpha_fault(cpppl_ctx* c, int sweep) {
+  if (!c || sweep < -1) return CPPPL_E_ARG;
+  c->inject_alpha_fault = sweep;
+  return CPPPL_OK;
+}
+
 CPPPL_API const char* cpppl_last_error(const cpppl_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+#ifndef CPPPL_SRC_HASH
+#define CPPPL_SRC_HASH "unknown"
+#endif
+CPPPL_API const char* cpppl_build_hash(void) { return CPPPL_SRC_HASH; }
 
 CPPPL_API const char* cpppl_status_str(cpppl_status s) {
   switch (s) {

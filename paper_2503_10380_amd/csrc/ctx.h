@@ -87,6 +87,15 @@ struct cpppl_ctx {
   int64_t rank_p = 0;
   bool norm_valid = false;
   bool ybeta_valid = false;
+  // tau holds KR(gamma, rho)^T t at the current gamma, rho in tau_dt: formed at
+  // the end of a sweep that evaluates E_CP, and reused by the next sweep
+  bool tau_valid = false;
+  cpppl::DType tau_dt = cpppl::DType::F64;
+  bool want_energy = false;  // sweeps evaluate E_CP (per-sweep energy history / energy stop)
+  // test hook: the W_alpha inverse forked early for sweep `inject_alpha_fault`
+  // of the next cpppl_als call reports a failed pivot (-1: off)
+  int inject_alpha_fault = -1;
+  bool inject_now = false;
   bool want_eta = true;  // sweeps evaluate eta (eq. N3_stopping)
   bool near_valid = false;  // the near-optimal cache holds an iterate
   cpppl::DType ybeta_dt = cpppl::DType::F64;

@@ -76,3 +76,54 @@ def test_status_strings_and_null_handling(lib):
     d = cp.Dims(4, 16, 48, 32)
     assert lib.cpppl_ws_in_dim(C.byref(d)) == 2 * (2 * 4 + 2 * 16)
     assert lib.cpppl_ws_out_dim(C.byref(d)) == 2 * 4 + 2 * 16
+
+
+def test_library_built_from_these_sources(lib):
+    """The library carries the hash of the sources it was built from, and the
+    binding refuses one whose hash differs from the tree's."""
+    from paper_2503_10380_amd import build
+    assert lib.cpppl_build_hash().decode() == build.source_hash()
+    assert len(build.source_hash()) == 64
+
+
+_CTYPES = {"int": C.c_int, "double": C.c_double, "int64_t": C.c_int64, "double*": C.POINTER(C.c_double)}
+
+
+def _struct_fields(name):
+    """(type, field) pairs of `typedef struct { ... } name;` in cpppl.h, in order."""
+    text = open(os.path.join(ROOT, "include", "cpppl.h")).read()
+    end = text.index("} " + name + ";")
+    body = text[text.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        m = re.match(r"(int64_t|int|double)\s*(\*?)\s*(.+)", decl)
+        base, star, names = m.group(1), m.group(2), m.group(3)
+        for part in names.split(","):
+            part = part.strip()
+            ptr = star or part.startswith("*")
+            fname = part.lstrip("*").strip()
+            arr = re.match(r"(\w+)\[(\d+)\]", fname)
+            if arr:
+                out.append((_CTYPES[base] * int(arr.group(2)), arr.group(1)))
+            else:
+                out.append((_CTYPES[base + ("*" if ptr else "")], fname))
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [("cpppl_als_opts", "AlsOpts"),
+                                          ("cpppl_als_report", "AlsReport"),
+                                          ("cpppl_dims", "Dims")])
+def test_binding_structs_match_header(cname, pyname):
+    """Field names, order and types of the binding's ctypes structures are the
+    header's (so the library and the binding agree on the layout)."""
+    want = _struct_fields(cname)
+    got = getattr(cp, pyname)._fields_
+    assert [f for _, f in want] == [f for f, _ in got]
+    for (wt, wf), (gf, gt) in zip(want, got):
+        assert C.sizeof(wt) == C.sizeof(gt), wf
+        assert getattr(wt, "_type_", None) == getattr(gt, "_type_", None), wf
+    assert "energy_hist" in [f for f, _ in cp.AlsReport._fields_]

@@ -77,3 +77,25 @@ def test_digest_groups_launches_and_calibrates(tmp_path):
         assert c["write_bytes_per_call"] == pytest.approx(kib * 1024)
         assert c["bytes_per_launch"] == pytest.approx(3.0 * kib * 1024 / n)
         assert c["calls"] == 2 * bench.SWEEP_GEMMS.count(cls)
+
+
+def test_dominant_class_breaks_near_ties_toward_the_weaker_kernel():
+    """The headline roofline goes to the class taking the most time, except
+    that classes within 5 % of it are tied and the one furthest from its own
+    roofline is reported; every class keeps its own roofline entry."""
+    cfg = synth.CONFIGS["C3"]
+    flops, nbytes = bench.class_flops(cfg), bench.class_bytes(cfg)
+    ms = {"kr_t2": 4.5, "y": 11.0, "z": 11.2, "m": 6.8, "g": 5.5, "h": 3.6}
+    rep = {"ms_class": dict(ms), "n_class": {"kr_t2": 20, "y": 40, "z": 40, "m": 40, "g": 20,
+                                             "h": 20}}
+    rl = bench.class_rooflines(rep, flops, nbytes)
+    assert set(rl) == set(bench.CLASSES)
+    # y moves fewer bytes than z in about the same time: further from its roofline
+    assert rl["y"]["frac"] < rl["z"]["frac"]
+    assert bench.dominant_class(rep, rl) == "y"
+    # without a near-tie the largest time share wins
+    rep["ms_class"]["z"] = 20.0
+    rl = bench.class_rooflines(rep, flops, nbytes)
+    assert bench.dominant_class(rep, rl) == "z"
+    # per launch: a class call of y is LAUNCHES["y"] launches
+    assert rl["y"]["avg_launch_ms"] == pytest.approx(11.0 / (40 * bench.LAUNCHES["y"]))

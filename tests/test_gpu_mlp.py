@@ -99,6 +99,38 @@ def test_one_adam_step_matches_reference(lib):
     assert np.abs(move_got).max() <= 1e-3 * (1 + 1e-5)
 
 
+def test_full_batch_adam_epochs_match_reference(lib):
+    """30 full-batch Adam epochs on the GPU (FP32 kernels) against
+    oracle.mlp.train (FP64) from the same parameters.  Adam moves a weight by
+    about lr sign(m) whatever the size of its gradient, so weights whose
+    gradient hovers near zero follow the rounding of that gradient: the
+    oracle's own trajectory, rerun with eps 1e-10 instead of 1e-8, moves the
+    per-epoch loss by up to 4e-5 relative and the weights' total movement by
+    1.6 % (norm-wise; 1 % even over the weights whose gradient stays above
+    1e-5).  The bounds follow: loss history to 1e-4 over the first 10 epochs
+    and 1e-3 over 30, movement to 5e-2."""
+    _say("mlp adam epochs")
+    m = _net(lib, capacity=64)
+    ps = _rand_params(SIZES, 6)
+    m.set_params(_pack(ps))
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((64, SIZES[0])).astype(np.float32)
+    t = rng.standard_normal((64, SIZES[-1])).astype(np.float32)
+    m.add_rows(x, t)
+    epochs = 30
+    hist = m.train(epochs, lr=1e-3)
+    want, want_hist = omlp.train(ps, x.astype(np.float64), t.astype(np.float64), epochs, lr=1e-3)
+    np.testing.assert_allclose(hist[:10], want_hist[:10], rtol=1e-4, atol=0)
+    np.testing.assert_allclose(hist, want_hist, rtol=1e-3, atol=0)
+    assert want_hist[-1] < 0.5 * want_hist[0]
+    base = _pack(ps).astype(np.float64)
+    move_got = m.get_params().astype(np.float64) - base
+    move_ref = np.concatenate([p.reshape(-1) for p in want]) - base
+    rel = np.linalg.norm(move_got - move_ref) / np.linalg.norm(move_ref)
+    _say(f"  movement rel diff {rel:.2e}")
+    assert rel <= 5e-2
+
+
 def test_training_reduces_loss_and_minibatches(lib):
     _say("mlp train")
     m = _net(lib, capacity=512, seed=11)

@@ -9,6 +9,8 @@ import pytest
 import oracle
 from oracle import fp8
 import synth
+from bounds import (N_ROUND_BF16, N_ROUND_FP8, abs_chain, assert_fp64, assert_lowp,
+                    chain_lengths)
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +60,7 @@ def test_singles_mttkrp_fp64(lib, name):
     ctx = _ctx(lib, cfg, inp, t1, b_vo)
     ctx.set_factors(*fs)
     for mode in range(4):
-        assert _rel(ctx.mttkrp(mode), oracle.mttkrp(r, fs, mode)) <= 1e-10
+        assert_fp64(ctx.mttkrp(mode), oracle.mttkrp(r, fs, mode))
     n2, e = ctx.norm_r2()
     n2_o, e_o = oracle.norm_r2_and_energy(r, tau)
     assert n2 == pytest.approx(n2_o, rel=1e-12)
@@ -98,15 +100,18 @@ def test_singles_low_precision(lib):
         ctx.set_factors(*fs)
         for mode in range(4):
             got = ctx.mttkrp(mode)
+            ks = chain_lengths(cfg.o, cfg.v, cfg.nx, mode)
             if prec == "bf16":
                 want = oracle.mttkrp_chain(tau, bvv, fs, mode, b_right=dbar)
+                err = assert_lowp(got, want, abs_chain(tau, bvv, fs, mode, b_right=dbar),
+                                  N_ROUND_BF16, ks, f"bf16 mode {mode}")
             else:
                 want = oracle.mttkrp_chain(tq, bq, fs, mode, b_right=dq)
-            err = _rel(got, want)
+                err = assert_lowp(got, want, abs_chain(tq, bq, fs, mode, b_right=dq),
+                                  N_ROUND_FP8, ks, f"fp8 mode {mode}")
             _say(f"  {prec} mode {mode}: {err:.2e}")
-            assert err <= 3e-2
-            assert _rel(ctx.mttkrp(mode, "fp64"),
-                        oracle.mttkrp_chain(tau, bvv, fs, mode, b_right=dbar)) <= 1e-10
+            assert_fp64(ctx.mttkrp(mode, "fp64"),
+                        oracle.mttkrp_chain(tau, bvv, fs, mode, b_right=dbar))
         ctx.close()
 
 
@@ -134,7 +139,7 @@ def test_singles_removed_and_reloaded(lib):
     ctx.warm_start(dt)
     r2 = oracle.form_r(tau + dt, inp.b_vv, b_right=dbar)
     for m in range(4):
-        assert _rel(ctx.mttkrp(m), oracle.mttkrp(r2, fs, m)) <= 1e-10
+        assert_fp64(ctx.mttkrp(m), oracle.mttkrp(r2, fs, m))
     ctx.close()
     plain_ctx.close()
 
@@ -170,9 +175,12 @@ def test_singles_full_size_rank1_tau_closed_form(lib, cfg_name):
     t2 = np.zeros((cfg.o, cfg.o, cfg.v, cfg.v))
     _, bvv, dbar = oracle.dress(t2[:1, :1], t1, b)  # Dbar only (tau is not formed here)
     cf = oracle.rank1_closed_form(u, u, p, p, bvv, dbar)
+    cf_abs = oracle.rank1_closed_form(np.abs(u), np.abs(u), np.abs(p), np.abs(p), np.abs(bvv),
+                                      np.abs(dbar))
     fs = synth.init_factors(cfg)
+    fs_abs = [np.abs(f) for f in fs]
     b_vo = np.ascontiguousarray(b[:, cfg.o:, :cfg.o])
-    for prec, tol in (("fp64", 1e-10), ("bf16", 3e-2)):
+    for prec in ("fp64", "bf16"):
         ctx = lib.Context(cfg.o, cfg.v, cfg.nx, cfg.rank, prec, singles=True)
         ctx.load_t2(t2)
         ctx.load_df(np.ascontiguousarray(bvv))
@@ -180,7 +188,12 @@ def test_singles_full_size_rank1_tau_closed_form(lib, cfg_name):
         ctx.set_factors(*fs)
         for mode in range(4):
             want = oracle.planted_mttkrp(cf, np.ones(cfg.nx), fs, mode)
-            err = _rel(ctx.mttkrp(mode), want)
-            _say(f"  {prec} mode {mode} rel err {err:.3e}")
-            assert err <= tol
+            got = ctx.mttkrp(mode)
+            _say(f"  {prec} mode {mode} rel err {_rel(got, want):.3e}")
+            if prec == "fp64":
+                assert_fp64(got, want)
+            else:
+                m_abs = oracle.planted_mttkrp(cf_abs, np.ones(cfg.nx), fs_abs, mode)
+                assert_lowp(got, want, m_abs, N_ROUND_BF16,
+                            chain_lengths(cfg.o, cfg.v, cfg.nx, mode), f"bf16 mode {mode}")
         ctx.close()
