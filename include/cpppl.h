@@ -235,6 +235,22 @@ CPPPL_API cpppl_status cpppl_fit(cpppl_ctx* ctx, double* fit, double* inner, dou
  * the reconstruction for the rest of the CCSD iteration).  Synchronises; drops
  * the cached Y_beta. */
 CPPPL_API cpppl_status cpppl_reconstruct(cpppl_ctx* ctx, double* out, int symmetrize, int on_device);
+/* One step of a CCD-like Jacobi iteration driven by the CP-approximated ladder
+ * (Section "Role of the Initial Guess"; the reconstruction and pair
+ * symmetrisation of Section "The CPD approximation of the PPL tensor-network"):
+ * with the CP tensor at the current factors, formed in FP64 as in
+ * cpppl_reconstruct and pair-symmetrised, R~_ijab = (CP_ijab + CP_jiba) / 2,
+ *   dt_ijab = (w_ijab + scale R~_ijab) / (e_i + e_j - e_a - e_b) - t_ijab,
+ * i.e. t + dt solves D t' = w + scale R~ for the driver w (o, o, v, v; e.g.
+ * (ia|jb)) and the orbital energies e_occ (o) and e_vir (v).  t is the
+ * context's doubles amplitudes (without the singles dressing); the context's t
+ * is not changed: pass dt to cpppl_warm_start to take the step, with the
+ * initial guess of the next ALS.  on_device: w, e_occ, e_vir and dt are device
+ * pointers (else host).  Synchronises; drops the cached Y_beta and tau.
+ * E_STATE without t, B and factors (or for a planted tensor). */
+CPPPL_API cpppl_status cpppl_jacobi_step(cpppl_ctx* ctx, const double* w, const double* e_occ,
+                                         const double* e_vir, double scale, double* dt,
+                                         int on_device);
 /* E_CP = sum_ijab CP_ijab t_ijab at the current factors, FP64. */
 CPPPL_API cpppl_status cpppl_energy(cpppl_ctx* ctx, double* e_cp);
 

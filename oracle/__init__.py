@@ -42,4 +42,5 @@ from .als import (  # noqa: F401
     eta,
 )
 from . import mlp  # noqa: F401
+from . import ccd  # noqa: F401
 from . import fp8  # noqa: F401

@@ -115,12 +115,13 @@ def eta(prev_factors, prev_lam, factors, lam) -> float:
 
 
 def cp_als(r_tensor, init, sweeps: int, norm_r2: float | None = None, t=None,
-           tol: float = 0.0, stop_rule: int = 0, mttkrp_fn=None):
+           tol: float = 0.0, stop_rule: int = 0, mttkrp_fn=None, on_sweep=None):
     """Textbook CP-ALS; returns (factors, lam, history dict).
 
     ``init`` = (gamma, rho, alpha, beta); lam starts at 1.  stop_rule 0 runs all
     sweeps, 1 stops when |fit_n - fit_{n-1}| < tol (eq. canon, with the absolute
-    value), 2 stops when eta < tol (eq. N3_stopping).
+    value), 2 stops when eta < tol (eq. N3_stopping).  ``on_sweep(factors, lam)``,
+    if given, sees the iterate after every sweep (copies).
     """
     from .ppl import energy_cp
     factors = [np.array(f, dtype=np.float64, copy=True) for f in init]
@@ -145,6 +146,8 @@ def cp_als(r_tensor, init, sweeps: int, norm_r2: float | None = None, t=None,
         hist["eta"].append(eta(prev_f, prev_lam, factors, lam))
         if t is not None:
             hist["energy"].append(energy_cp(t, factors, lam))
+        if on_sweep is not None:
+            on_sweep([f.copy() for f in factors], lam.copy())
         if stop_rule == 1 and prev_fit is not None and abs(fit - prev_fit) < tol:
             break
         if stop_rule == 2 and hist["eta"][-1] < tol:

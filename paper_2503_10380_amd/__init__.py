@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH):
         "cpppl_mttkrp": (st, [_P, C.c_int, C.c_int, _P, C.c_int]),
         "cpppl_fit": (st, [_P, _D, _D, _D]),
         "cpppl_energy": (st, [_P, _D]),
+        "cpppl_jacobi_step": (st, [_P, _P, _P, _P, C.c_double, _P, C.c_int]),
         "cpppl_reconstruct": (st, [_P, _P, C.c_int, C.c_int]),
         "cpppl_mlp_create": (st, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_uint64, C.c_int,
                                   C.POINTER(_P)]),
@@ -339,6 +340,28 @@ class Context:
         self._call("cpppl_reconstruct", _ptr_host(res), int(bool(symmetrize)), 0)
         return res
 
+    def jacobi_step(self, w, e_occ, e_vir, scale, out=None):
+        """dt of one CCD-like Jacobi step with the pair-symmetrised CP ladder:
+        (w + scale R~) / D - t.  Device inputs (torch) give a device dt
+        (into `out` when given); host inputs a numpy dt."""
+        keep = []
+        shape = (self.o, self.o, self.v, self.v)
+        pw, dw = self._arg(w, shape, keep)
+        po, do = self._arg(e_occ, (self.o,), keep)
+        pv, dv = self._arg(e_vir, (self.v,), keep)
+        if len({dw, do, dv}) != 1:
+            raise ValueError("w, e_occ and e_vir must all be on the host or all on the device")
+        if dw:
+            torch = _torch()
+            if out is None:
+                out = torch.empty(shape, dtype=torch.float64, device=w.device)
+            po_, _ = self._arg(out, shape, keep)
+            self._call("cpppl_jacobi_step", pw, po, pv, C.c_double(scale), po_, 1)
+            return out
+        res = np.empty(shape)
+        self._call("cpppl_jacobi_step", pw, po, pv, C.c_double(scale), _ptr_host(res), 0)
+        return res
+
     def energy(self):
         e = C.c_double()
         self._call("cpppl_energy", C.byref(e))
@@ -364,6 +387,48 @@ class Context:
 
     def training_rows(self, mlp):
         self._call("cpppl_ws_training_rows", mlp.h)
+
+
+GUESSES = ("random", "optimal", "near_optimal")
+
+
+def ccd_loop(ctx, w, e_occ, e_vir, scale, steps, guess="optimal", seed=0, tol=1e-3,
+             max_sweeps=100, on_step=None):
+    """A CCD-like Jacobi iteration with the CP-approximated ladder, as a
+    sequence of library calls: per CC step k = 1..steps, ALS (|dfit| < tol, at
+    most max_sweeps) on the context's current t, then cpppl_jacobi_step for
+    dt, then cpppl_warm_start(dt) with the next step's initial guess --
+    "random" (a fresh cpppl_init_random(seed + k + 1) guess), "optimal" (the
+    converged factors) or "near_optimal" (the near-optimal cache, kept by the
+    ALS calls).  CC step 1 starts from cpppl_init_random(seed + 1).  w, e_occ,
+    e_vir: torch CUDA float64 tensors (the driver (ia|jb) and the orbital
+    energies); the context must hold t^(0) and B.  Returns one record per CC
+    step (sweeps, fit, the guess it started from); on_step(k, dt, record) sees
+    each step's dt (device tensor) before it is applied."""
+    if guess not in GUESSES:
+        raise ValueError(f"guess must be one of {GUESSES}")
+    hist = []
+    used = "random"
+    ctx.init_random(seed + 1)
+    for k in range(1, steps + 1):
+        rep = ctx.als(max_sweeps, stop_rule=1, tol=tol, near_cache=guess == "near_optimal")
+        dt = ctx.jacobi_step(w, e_occ, e_vir, scale)
+        rec = {"sweeps": rep["sweeps"], "fit": rep["fit"], "guess": used,
+               "ms_als": rep["ms_total"]}
+        if on_step is not None:
+            on_step(k, dt, rec)
+        hist.append(rec)
+        if guess == "random":
+            ctx.warm_start(dt, WS_PLAIN)
+            ctx.init_random(seed + k + 1)
+            used = "random"
+        elif guess == "near_optimal":
+            chosen = ctx.warm_start(dt, WS_NEAR_OPTIMAL)
+            used = "near_optimal" if chosen == WS_NEAR_OPTIMAL else "optimal"
+        else:
+            ctx.warm_start(dt, WS_PLAIN)
+            used = "optimal"
+    return hist
 
 
 class MLP:

@@ -119,6 +119,7 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   p.dt64T = add(o2v2 * 8);
   p.dt16 = bf ? add(o2v2 * 2) : 0;
   p.dt16T = bf ? add(o2v2 * 2) : 0;
+  p.eorb = add((size_t)(o + v) * 8);
   // intermediates, sized for FP64 and shared by the BF16 path
   const size_t tau_e = (size_t)(R * v * v), y_e = (size_t)(R * X * v);
   const size_t z_e = (size_t)(R * std::max(X, v) * v);  // Z, and G (R v^2) aliased on it
@@ -1407,6 +1408,48 @@ CPPPL_API cpppl_status cpppl_reconstruct(cpppl_ctx* c, double* out, int symmetri
   if (symmetrize) symmetrize_pairs(dst, o, v, c->stream);
   if (!on_device)
     CPPPL_HIP(hipMemcpyAsync(out, dst, (size_t)(o * o * v * v) * 8, hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  API_CATCH(c)
+}
+
+CPPPL_API cpppl_status cpppl_jacobi_step(cpppl_ctx* c, const double* w, const double* e_occ,
+                                         const double* e_vir, double scale, double* dt,
+                                         int on_device) {
+  API_TRY(c)
+  need_ws(c);
+  if (!w || !e_occ || !e_vir || !dt) throw std::invalid_argument("NULL argument");
+  if (!std::isfinite(scale)) throw std::invalid_argument("scale must be finite");
+  if (c->planted || !c->have_t || !c->have_b) throw StatusError(CPPPL_E_STATE, "load t2 and B first");
+  if (!c->have_factors) throw StatusError(CPPPL_E_STATE, "set the factors first");
+  const Plan& p = c->plan;
+  const int64_t o = c->d.o, v = c->d.v, R = c->d.rank;
+  const int64_t n = o * o * v * v;
+  // the doubles amplitudes (the raw t2 when a singles dressing is on)
+  const double* t = c->at<double>(c->singles_on ? p.t2raw : p.t64);
+  load_device_or_host(c, c->at(p.eorb), e_occ, (size_t)o * 8, on_device);
+  load_device_or_host(c, c->at<double>(p.eorb) + o, e_vir, (size_t)v * 8, on_device);
+  const double* wd = w;
+  if (!on_device) {  // stage w where dt is formed
+    load_device_or_host(c, c->at(p.dt64), w, (size_t)n * 8, 0);
+    wd = c->at<double>(p.dt64);
+  }
+  // CP (FP64, one GEMM of two Khatri-Rao products, as in cpppl_reconstruct) into dt64T
+  khatri_rao_t(c->at<double>(p.FT[0]), c->at<double>(p.FT[1]), o, R, c->at(p.Kt), DType::F64,
+               c->stream, nullptr, c->at<double>(p.lam));
+  khatri_rao_t(c->at<double>(p.FT[2]), c->at<double>(p.FT[3]), v, R, c->at(p.big), DType::F64,
+               c->stream);
+  c->ybeta_valid = c->tau_valid = false;
+  Gemm g;
+  g.M = o * o; g.N = v * v; g.K = R;
+  g.A = c->at(p.Kt); g.sam = 1; g.sak = o * o;
+  g.B = c->at(p.big); g.sbk = v * v; g.sbn = 1;
+  g.C = c->at(p.dt64T); g.scm = v * v; g.ctype = DType::F64;
+  gemm_f64(g, c->stream);
+  double* out = on_device ? dt : c->at<double>(p.dt64);
+  jacobi_delta(c->at<double>(p.dt64T), wd, c->at<double>(p.eorb), c->at<double>(p.eorb) + o, scale,
+               t, out, o, v, c->stream);
+  if (!on_device)
+    CPPPL_HIP(hipMemcpyAsync(dt, out, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
   sync(c);
   API_CATCH(c)
 }

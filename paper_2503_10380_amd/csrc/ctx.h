@@ -37,6 +37,8 @@ struct Plan {
   // warm start: previous factors, first-order change, features / targets, dt layouts
   size_t wsF[4], wsLam, wsFeat, wsOut, wsD[4];
   size_t dt64, dt64T, dt16, dt16T;
+  // orbital energies of the Jacobi step: e_occ (o) then e_vir (v)
+  size_t eorb;
 };
 
 enum Scal {  // slots of the device scalar block

@@ -35,6 +35,11 @@ void quantize_e4m3(const double* x, uint8_t* q, int64_t n, const float* scale, i
                    int64_t mod, int64_t grp, hipStream_t s);
 // out[X*v + q] = scale[X].
 void expand_scales(const float* scale, float* out, int64_t nx, int64_t v, hipStream_t s);
+// dt[ijab] = (w[ijab] + scale (cp[ijab] + cp[jiba]) / 2) / (e_occ[i] + e_occ[j] - e_vir[a]
+// - e_vir[b]) - t[ijab]: one Jacobi step of D t = w + scale R(t) with the pair-symmetrised
+// CP tensor for R, as a change of t (o x o x v x v, FP64; dt may alias w).
+void jacobi_delta(const double* cp, const double* w, const double* e_occ, const double* e_vir,
+                  double scale, const double* t, double* dt, int64_t o, int64_t v, hipStream_t s);
 // tau[i][j][c][d] = t2[i][j][c][d] + t1[i][c] t1[j][d] (t1 is o x v), FP64.
 void dress_tau(const double* t2, const double* t1, double* tau, int64_t o, int64_t v, hipStream_t s);
 // w = g1 .* g2 .* g3 (n elements); g3 may be null.

@@ -120,6 +120,22 @@ __global__ void symmetrize_pairs_kernel(double* x, int64_t o, int64_t v) {
   }
 }
 
+// dt[ijab] = (w[ijab] + s (cp[ijab] + cp[jiba]) / 2) / (e_i + e_j - e_a - e_b) - t[ijab]
+__global__ void jacobi_delta_kernel(const double* cp, const double* w, const double* e_occ,
+                                    const double* e_vir, double s, const double* t, double* dt,
+                                    int64_t o, int64_t v) {
+  const int64_t n = o * o * v * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ij = e / (v * v), ab = e % (v * v);
+    const int64_t i = ij / o, j = ij % o, a = ab / v, b = ab % v;
+    const int64_t f = (j * o + i) * v * v + b * v + a;
+    const double ladder = 0.5 * (cp[e] + cp[f]);
+    const double d = e_occ[i] + e_occ[j] - e_vir[a] - e_vir[b];
+    dt[e] = (w[e] + s * ladder) / d - t[e];
+  }
+}
+
 // One work-group per row: the least power of two 2^e (e in [-126, 127]) with
 // max |x| <= 448 * 2^e, i.e. the row scaled by 2^-e fits the e4m3 range.
 __global__ __launch_bounds__(TPB) void e4m3_scale_kernel(const double* __restrict__ x, int64_t len,
@@ -541,6 +557,15 @@ void symmetrize_pairs(double* x, int64_t o, int64_t v, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(symmetrize_pairs_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, x, o, v);
   CPPPL_LAUNCH_CHECK("symmetrize_pairs");
+}
+
+void jacobi_delta(const double* cp, const double* w, const double* e_occ, const double* e_vir,
+                  double scale, const double* t, double* dt, int64_t o, int64_t v, hipStream_t s) {
+  const int64_t n = o * o * v * v;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(jacobi_delta_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, cp, w, e_occ, e_vir,
+                     scale, t, dt, o, v);
+  CPPPL_LAUNCH_CHECK("jacobi_delta");
 }
 
 void dress_tau(const double* t2, const double* t1, double* tau, int64_t o, int64_t v, hipStream_t s) {

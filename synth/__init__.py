@@ -17,4 +17,6 @@ from .generator import (  # noqa: F401
     rank1_t2,
     make_singles,
     rank1_singles,
+    exchange_integrals,
+    ccd_scale,
 )

@@ -191,3 +191,24 @@ def rank1_t2(cfg: Config, seed: int = 0):
     q = rng.standard_normal(cfg.v)
     t = np.einsum("i,j,c,d->ijcd", u, w, p, q)
     return t, (u, w, p, q)
+
+
+def exchange_integrals(inp: "Inputs") -> np.ndarray:
+    """w[i, j, a, b] = (ia|jb) = sum_X B^X_ia B^X_jb: the driver of the synthetic
+    CCD-like iteration (the numerator of the MP2 amplitudes)."""
+    cfg = inp.cfg
+    o, v, nx = cfg.o, cfg.v, cfg.nx
+    bov = np.ascontiguousarray(inp.b_full[:, :o, o:]).reshape(nx, o * v)
+    return np.ascontiguousarray((bov.T @ bov).reshape(o, v, o, v).transpose(0, 2, 1, 3))
+
+
+def ccd_scale(inp: "Inputs") -> float:
+    """Scale s of the ladder term in the synthetic CCD-like iteration,
+    s = min|D| / (2 sum_X ||B^X_vv||_2^2).  The ladder maps t_ij to
+    sum_X B^X t_ij B^X^T, whose norm is at most sum_X ||B^X||_2^2, so the exact
+    Jacobi map t -> (w + s R(t)) / D contracts by at least 1/2."""
+    o = inp.cfg.o
+    d = (inp.e_occ[:, None, None, None] + inp.e_occ[None, :, None, None]
+         - inp.e_vir[None, None, :, None] - inp.e_vir[None, None, None, :])
+    spec = sum(float(np.linalg.norm(inp.b_full[x, o:, o:], 2)) ** 2 for x in range(inp.cfg.nx))
+    return float(np.abs(d).min()) / (2.0 * spec)
