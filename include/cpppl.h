@@ -320,6 +320,28 @@ CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* ctx, const double* dt, int on
  * column, sign-aligned) into the network's training set. */
 CPPPL_API cpppl_status cpppl_ws_training_rows(cpppl_ctx* ctx, cpppl_mlp* mlp);
 
+/* ---- MTTKRP without allocation ------------------------------------------------ */
+
+/* For callers that cannot allocate device memory (code under HIP stream / graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * matrix-free MTTKRP of cpppl_mttkrp, for one mode (0 i, 1 j, 2 a, 3 b), with
+ * no context and no allocation.  All pointers are device pointers on the
+ * current HIP device, row-major FP64, caller-owned: t (o, o, v, v), b (nx, v, v),
+ * fi, fj (o x R), fa, fb (v x R), m_out (n_mode x R, written).  Work is
+ * enqueued on hip_stream (a hipStream_t; NULL = default stream); the call does
+ * not synchronise.  Intermediates live in one 64 MiB device array of the
+ * library (one per device, held until the process ends), so a problem must fit
+ * it: modes a, b need 2oR + Ro^2 + Rv^2 + Xv^2 + 2RXv + Rv doubles, modes i, j
+ * oR + 2RXv + Rv^2 + Ro^2 + Ro (each term rounded up to 32), at most 8 Mi
+ * doubles; larger problems return CPPPL_E_NOMEM before any work is enqueued.
+ * Every call on a device uses that device's array: calls that overlap on one
+ * device (other streams or threads) race and must be serialised by the caller.
+ * E_ARG for NULL pointers, a bad mode or bad dims; E_HIP for a launch error. */
+CPPPL_API cpppl_status cpppl_mttkrp_noalloc(const cpppl_dims* dims, const double* t,
+                                            const double* b, const double* fi, const double* fj,
+                                            const double* fa, const double* fb, int mode,
+                                            double* m_out, void* hip_stream);
+
 /* ---- errors and build identity --------------------------------------------- */
 CPPPL_API const char* cpppl_last_error(const cpppl_ctx* ctx);
 CPPPL_API const char* cpppl_status_str(cpppl_status s);

@@ -121,6 +121,7 @@ def load_library(path: str = LIB_PATH):
         "cpppl_last_error": (C.c_char_p, [_P]),
         "cpppl_status_str": (C.c_char_p, [C.c_int]),
         "cpppl_build_hash": (C.c_char_p, []),
+        "cpppl_mttkrp_noalloc": (st, [C.POINTER(Dims), _P, _P, _P, _P, _P, _P, C.c_int, _P, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -387,6 +388,30 @@ class Context:
 
     def training_rows(self, mlp):
         self._call("cpppl_ws_training_rows", mlp.h)
+
+
+def mttkrp_noalloc(t, b, fi, fj, fa, fb, mode, out=None, stream=None):
+    """cpppl_mttkrp_noalloc on torch CUDA float64 tensors (contiguous):
+    t (o, o, v, v), b (X, v, v), fi, fj (o, R), fa, fb (v, R); returns (or
+    fills) the (n_mode, R) device tensor.  Enqueued on `stream` (default: the
+    current stream); nothing is allocated by the library."""
+    torch = _torch()
+    lib = load_library()
+    o, v, nx, rank = t.shape[0], t.shape[2], b.shape[0], fi.shape[1]
+    for x in (t, b, fi, fj, fa, fb):
+        if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
+            raise ValueError("device float64 contiguous tensors expected")
+    n = (o, o, v, v)[mode]
+    if out is None:
+        out = torch.empty((n, rank), dtype=torch.float64, device=t.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(t.device)
+    d = Dims(o, v, nx, rank, 0)
+    st = lib.cpppl_mttkrp_noalloc(C.byref(d), *[_P(x.data_ptr()) for x in (t, b, fi, fj, fa, fb)],
+                                  int(mode), _P(out.data_ptr()), _P(stream.cuda_stream))
+    if st != 0:
+        raise CppplError(st, "cpppl_mttkrp_noalloc failed")
+    return out
 
 
 GUESSES = ("random", "optimal", "near_optimal")
