@@ -565,6 +565,59 @@ def warmstart_experiment(cp, torch, args):
             "wall_s": time.perf_counter() - t0}
 
 
+def ccd_experiment(cp, torch, args):
+    """The CCD-like Jacobi iteration on the pair-symmetrised CP ladder (C2 by
+    default): t^(k) = (w + s R~(t^(k-1))) / D from the MP2 amplitudes, ALS to
+    |dfit| < --ccd-tol per CC step (at most --ccd-cap sweeps, FP64), for each of
+    the paper's three initial guesses.  Reported per CC step: ALS sweeps, fit,
+    the guess used, E = <w, t> and its change, and ||dt|| (E and ||dt|| are
+    diagnostics computed with torch on the amplitudes the library returns)."""
+    cfg = synth.CONFIGS[args.config]
+    inp = synth.make_inputs(cfg)
+    w = synth.exchange_integrals(inp)
+    s = synth.ccd_scale(inp)
+    dev = [torch.tensor(x, device="cuda") for x in (w, inp.e_occ, inp.e_vir)]
+    out = {"metric": "CCD-like Jacobi loop with the CP ladder: ALS sweeps per CC step by initial guess",
+           "config": {"workload": cfg.name, "o": cfg.o, "v": cfg.v, "nx": cfg.nx, "rank": cfg.rank,
+                      "als": "fp64", "tol": args.ccd_tol, "cap": args.ccd_cap,
+                      "cc_steps": args.ccd_steps, "scale": s},
+           "guesses": {}}
+    for guess in cp.GUESSES:
+        ctx = cp.Context(cfg.o, cfg.v, cfg.nx, cfg.rank, "fp64")
+        ctx.load_t2(torch.tensor(inp.t, device="cuda"))
+        ctx.load_df(torch.tensor(inp.b_vv, device="cuda"))
+        t_cur = torch.tensor(inp.t, device="cuda")
+        e_prev = float(torch.sum(dev[0] * t_cur))
+        rows = []
+
+        def on_step(k, dt, rec):
+            nonlocal t_cur
+            t_cur = t_cur + dt
+            rec["energy"] = float(torch.sum(dev[0] * t_cur))
+            rec["dt_norm"] = float(torch.linalg.vector_norm(dt))
+
+        t0 = time.perf_counter()
+        hist = cp.ccd_loop(ctx, *dev, s, args.ccd_steps, guess=guess, seed=11, tol=args.ccd_tol,
+                           max_sweeps=args.ccd_cap, on_step=on_step)
+        wall = time.perf_counter() - t0
+        for h in hist:
+            h["d_energy"] = h["energy"] - e_prev
+            e_prev = h["energy"]
+            rows.append(h)
+        ctx.close()
+        later = [h["sweeps"] for h in rows[1:]]
+        out["guesses"][guess] = {
+            "steps": rows, "wall_s": wall,
+            "sweeps_first_step": rows[0]["sweeps"],
+            "mean_sweeps_later_steps": float(np.mean(later)) if later else None,
+            "fit_first": rows[0]["fit"], "fit_last": rows[-1]["fit"],
+            "last_abs_d_energy": abs(rows[-1]["d_energy"]),
+        }
+        print(json.dumps({guess: out["guesses"][guess]["mean_sweeps_later_steps"]}), file=sys.stderr,
+              flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -589,7 +642,11 @@ def main():
                     help="precision ablation: fit-change floor of the FP8 sweeps")
     ap.add_argument("--ablation-tol", type=float, default=1e-5,
                     help="precision ablation: |dfit| tolerance of the FP64 phase")
-    ap.add_argument("--experiment", choices=["warmstart", "precision"],
+    ap.add_argument("--ccd-steps", type=int, default=10)
+    ap.add_argument("--ccd-tol", type=float, default=1e-3,
+                    help="ccd: ALS stop |dfit| < tol per CC step (the paper's 1e-3)")
+    ap.add_argument("--ccd-cap", type=int, default=100)
+    ap.add_argument("--experiment", choices=["warmstart", "precision", "ccd"],
                     help="warmstart: the learned warm-start experiment (C4 unless --config); "
                          "precision: the FP64 / BF16 / FP8 ablation (C5 unless --config)")
     ap.add_argument("--ws-epochs", type=int, default=300)
@@ -609,6 +666,12 @@ def main():
         import paper_2503_10380_amd as cp
         args.config = args.config or "C4"
         print(json.dumps(warmstart_experiment(cp, torch, args)))
+        return
+    if args.experiment == "ccd":
+        import torch
+        import paper_2503_10380_amd as cp
+        args.config = args.config or "C2"
+        print(json.dumps(ccd_experiment(cp, torch, args)))
         return
     if args.experiment == "precision":
         import torch

@@ -289,6 +289,19 @@ CPPPL_API cpppl_status cpppl_mlp_get_rows(cpppl_mlp* mlp, float* x, float* y, in
  * batch, no shuffle).  loss_hist (host, epochs entries) may be NULL. */
 CPPPL_API cpppl_status cpppl_mlp_train(cpppl_mlp* mlp, int epochs, float lr, int64_t batch,
                                        uint64_t seed, float* loss_hist);
+/* Standardise the stored rows for training and remember how: per input column
+ * x' = (x - mean) / std and per output column y' = y / rms over the stored rows
+ * (a constant or zero column keeps scale 1).  Rows added later are
+ * standardised on the way in, and the learned warm start applies the same map
+ * to its features and undoes it on the network's output; cpppl_mlp_forward /
+ * cpppl_mlp_grad / cpppl_mlp_train act on the standardised numbers.  Saved and
+ * loaded with the parameters.  E_STATE if already standardised, E_ARG with
+ * fewer than two rows. */
+CPPPL_API cpppl_status cpppl_mlp_standardize(cpppl_mlp* mlp);
+/* The standardisation (host arrays; any may be NULL): x_mu, x_inv (in_dim:
+ * mean and 1/std) and y_sc (out_dim: rms).  E_STATE if not standardised. */
+CPPPL_API cpppl_status cpppl_mlp_get_standardization(cpppl_mlp* mlp, float* x_mu, float* x_inv,
+                                                     float* y_sc);
 CPPPL_API cpppl_status cpppl_mlp_save(cpppl_mlp* mlp, const char* path);
 CPPPL_API cpppl_status cpppl_mlp_load(cpppl_mlp* mlp, const char* path);
 
@@ -301,23 +314,27 @@ enum {
                                while no cache exists.  No features are formed. */
 };
 
-/* Feature width of the warm-start network for these dims: 2 (2o + 2v). */
+/* Feature width of the warm-start network for these dims: 2 (2o + 2v) + 1. */
 CPPPL_API int64_t cpppl_ws_in_dim(const cpppl_dims* dims);
 CPPPL_API int64_t cpppl_ws_out_dim(const cpppl_dims* dims);
 
 /* Advance the amplitudes by dt (o, o, v, v) and warm-start the factors.
  * Computes the matrix-free MTTKRP of dR (the PPL tensor of dt) at the current
- * (previous converged) factors, forms per-column features [F, dR-MTTKRP W^-1 /
- * lambda] for the four modes, then sets t <- t + dt and the factors to the
- * chosen candidate.  For LEARNED, the candidate with the lower
- * ||CP||^2 - 2 <R, CP> (R of the new t) between the network's and PLAIN is
- * kept; *chosen reports it (a CPPPL_WS_* value).  The features are kept for
+ * (previous converged) factors, forms per-column features [F, D, log10
+ * (||dt|| / ||t||)] with D = dR-MTTKRP W^-1 / lambda the first-order change
+ * of each factor column (modes i, j, a, b), then sets t <- t + dt and the
+ * factors to the chosen candidate.  For LEARNED the candidate is F + the
+ * network's correction (through the network's standardisation, see
+ * cpppl_mlp_standardize); for LEARNED and FIRST_ORDER the candidate replaces
+ * PLAIN only if its ||CP||^2 - 2 <R, CP> (R of the new t) is lower; *chosen
+ * reports the start kept (a CPPPL_WS_* value).  The raw features are kept for
  * cpppl_ws_training_rows.  mlp may be NULL unless strategy is LEARNED. */
 CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* ctx, const double* dt, int on_device,
                                         int strategy, cpppl_mlp* mlp, int* chosen);
-/* After ALS from a warm start: write the R training rows of that step (features
- * of the warm start, and targets = converged minus previous factors, per
- * column, sign-aligned) into the network's training set. */
+/* After ALS from a warm start: write the R training rows of that step (the
+ * raw features of the warm start, and targets = the current (converged)
+ * minus the previous factors, per column, sign-aligned) into the network's
+ * training set (standardised on the way in if the network is). */
 CPPPL_API cpppl_status cpppl_ws_training_rows(cpppl_ctx* ctx, cpppl_mlp* mlp);
 
 /* ---- MTTKRP without allocation ------------------------------------------------ */

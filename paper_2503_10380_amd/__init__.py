@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH):
         "cpppl_mlp_num_rows": (st, [_P, C.POINTER(C.c_int64)]),
         "cpppl_mlp_get_rows": (st, [_P, _P, _P, C.c_int]),
         "cpppl_mlp_train": (st, [_P, C.c_int, C.c_float, C.c_int64, C.c_uint64, _P]),
+        "cpppl_mlp_standardize": (st, [_P]),
+        "cpppl_mlp_get_standardization": (st, [_P, _P, _P, _P]),
         "cpppl_mlp_save": (st, [_P, C.c_char_p]),
         "cpppl_mlp_load": (st, [_P, C.c_char_p]),
         "cpppl_ws_in_dim": (C.c_int64, [C.POINTER(Dims)]),
@@ -541,6 +543,20 @@ class MLP:
         self._check(self.lib.cpppl_mlp_train(self.h, epochs, C.c_float(lr), batch, seed,
                                              hist.ctypes.data_as(_P)))
         return hist
+
+    def standardize(self):
+        """Standardise the stored rows (per-column centring / scaling) and keep
+        the map for the learned warm start."""
+        self._check(self.lib.cpppl_mlp_standardize(self.h))
+
+    def standardization(self):
+        """(x_mu, x_inv, y_sc) of a standardised network."""
+        mu = np.empty(self.in_dim, dtype=np.float32)
+        inv = np.empty(self.in_dim, dtype=np.float32)
+        sc = np.empty(self.out_dim, dtype=np.float32)
+        self._check(self.lib.cpppl_mlp_get_standardization(
+            self.h, mu.ctypes.data_as(_P), inv.ctypes.data_as(_P), sc.ctypes.data_as(_P)))
+        return mu, inv, sc
 
     def save(self, path):
         self._check(self.lib.cpppl_mlp_save(self.h, str(path).encode()))

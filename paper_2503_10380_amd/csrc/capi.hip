@@ -113,7 +113,8 @@ Plan build_plan(const cpppl_dims& d, cpppl_precision prec) {
   const int64_t nmax = std::max(o, v);
   p.MT = add((size_t)nmax * R * 8);
   p.stage = add((size_t)std::max<int64_t>(nmax * R, R * R) * 8);
-  p.wsFeat = add((size_t)R * 2 * (2 * o + 2 * v) * 4);
+  p.wsFeat = add((size_t)R * (2 * (2 * o + 2 * v) + 1) * 4);
+  p.wsFeatStd = add((size_t)R * (2 * (2 * o + 2 * v) + 1) * 4);
   p.wsOut = add((size_t)R * (2 * o + 2 * v) * 4);
   p.dt64 = add(o2v2 * 8);
   p.dt64T = add(o2v2 * 8);
@@ -1045,6 +1046,9 @@ bool ws_install_near_cache(cpppl_ctx* c) {
   return true;
 }
 void ws_sync(cpppl_ctx* c) { sync(c); }
+const double* ws_t_doubles(cpppl_ctx* c) {
+  return c->at<double>(c->singles_on ? c->plan.t2raw : c->plan.t64);
+}
 int64_t ws_nmode(const cpppl_dims& d, int m) { return nmode(d, m); }
 
 }  // namespace cpppl

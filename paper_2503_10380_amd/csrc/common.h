@@ -25,6 +25,16 @@ __host__ __device__ inline float bf16_to_f32(bf16_t h) {
   return __builtin_bit_cast(float, u);
 }
 
+// Two floats to packed bfloat16 (round to nearest even), one v_cvt_pk_bf16_f32
+// on gfx950: `lo` in the low half.  The same rounding as f32_to_bf16 for every
+// finite value; the software form compiles to a NaN test and a branch per value.
+__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  typedef float f2_t __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
+  const f2_t x = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, b2_t));
+}
+
 template <typename T> struct Conv;
 template <> struct Conv<double> {
   __device__ static inline double from_f64(double x) { return x; }

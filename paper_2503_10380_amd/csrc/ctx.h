@@ -35,7 +35,7 @@ struct Plan {
   // planted CP tensor
   size_t FpT[4], lamp, Cp;
   // warm start: previous factors, first-order change, features / targets, dt layouts
-  size_t wsF[4], wsLam, wsFeat, wsOut, wsD[4];
+  size_t wsF[4], wsLam, wsFeat, wsFeatStd, wsOut, wsD[4];
   size_t dt64, dt64T, dt16, dt16T;
   // orbital energies of the Jacobi step: e_occ (o) then e_vir (v)
   size_t eorb;
@@ -49,8 +49,8 @@ enum Scal {  // slots of the device scalar block
   S_ENERGY = 20,
   S_CP2_PREV = 21,
   S_JUDGE = 24,  // 24..28 judge fit scalars
-  S_WS_SCALE = 30,  // feature / target scale of the warm-start network
-  S_WS_SUMSQ = 32,  // 32..33 scratch for the scale
+  S_WS_SCALE = 30,  // log10 of the relative step ||dt|| / ||t|| (a warm-start feature)
+  S_WS_SUMSQ = 32,  // 32..33: ||dt||^2 and ||t||^2
   S_COUNT = 64
 };
 

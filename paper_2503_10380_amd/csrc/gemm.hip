@@ -615,10 +615,21 @@ void gemm_bf16_kernel(const KArgs a) {
               for (int j = 0; j < TN; ++j) {
                 const int lm = (wm & 1) * WM + i * 16 + lr;
                 const int ln = wn * WN + j * 16 + lc;
-                const uint32_t w0 = (uint32_t)f32_to_bf16(alpha * acc[i][j][0]) |
-                                    ((uint32_t)f32_to_bf16(alpha * acc[i][j][1]) << 16);
-                const uint32_t w1 = (uint32_t)f32_to_bf16(alpha * acc[i][j][2]) |
-                                    ((uint32_t)f32_to_bf16(alpha * acc[i][j][3]) << 16);
+                // The hardware conversion (one instruction per pair) took Y, Z
+                // and G 2-8 % faster alone at o = 32, v = 256, X = 768, R = 1024
+                // (the sweep +1 %); in the 8-wave tile it pushed the kernel past
+                // 128 registers into scratch (tau 9 % slower), so that tile keeps
+                // the software rounding (the same result for every finite value).
+                uint32_t w0, w1;
+                if constexpr (WGM == 4) {
+                  w0 = (uint32_t)f32_to_bf16(alpha * acc[i][j][0]) |
+                       ((uint32_t)f32_to_bf16(alpha * acc[i][j][1]) << 16);
+                  w1 = (uint32_t)f32_to_bf16(alpha * acc[i][j][2]) |
+                       ((uint32_t)f32_to_bf16(alpha * acc[i][j][3]) << 16);
+                } else {
+                  w0 = pack_bf16x2(alpha * acc[i][j][0], alpha * acc[i][j][1]);
+                  w1 = pack_bf16x2(alpha * acc[i][j][2], alpha * acc[i][j][3]);
+                }
                 *(uint2*)&Cs[lm * LDC2 + ln] = make_uint2(w0, w1);
               }
           }

@@ -28,6 +28,12 @@ struct cpppl_mlp {
   float* work = nullptr;
   float* scal = nullptr;      // device scalars (loss partials)
   float* host_scal = nullptr; // pinned
+  // standardisation of the warm-start rows (cpppl_mlp_standardize): inputs
+  // x' = (x - x_mu) x_inv per column, targets y' = y / y_sc per column
+  bool standardized = false;
+  float* x_mu = nullptr;
+  float* x_inv = nullptr;
+  float* y_sc = nullptr;
   std::string err;
 };
 
@@ -38,7 +44,12 @@ void mlp_forward_dev(cpppl_mlp* m, const float* x, int64_t n, float* y, hipStrea
 // Loss (device scalar in m->scal[0]) and gradients (m->grads) for rows x, targets y.
 void mlp_loss_grad_dev(cpppl_mlp* m, const float* x, const float* y, int64_t n, hipStream_t s);
 void mlp_ensure_work(cpppl_mlp* m, int64_t rows);
-// Append device rows to the training set.
+// In place: x[r][:] = (x[r][:] - x_mu) x_inv (row stride ldx), a no-op unless standardised.
+void mlp_std_x_dev(cpppl_mlp* m, float* x, int64_t ldx, int64_t n, hipStream_t s);
+// In place: y[r][:] *= y_sc (row stride ldy), a no-op unless standardised.
+void mlp_unscale_y_dev(cpppl_mlp* m, float* y, int64_t ldy, int64_t n, hipStream_t s);
+// Append device rows to the training set (standardised on the way in once the
+// network is).
 void mlp_append_dev(cpppl_mlp* m, const float* x, int64_t ldx, const float* y, int64_t ldy,
                     int64_t n, hipStream_t s);
 

@@ -1,6 +1,7 @@
 // Warm-start network: a ReLU multi-layer perceptron applied to every rank
 // column independently, FP32, with hand-written forward / backward / Adam
-// kernels.  y = h_{L-1} W_L^T + b_L, h_l = relu(h_{l-1} W_l^T + b_l), loss =
+// kernels (the layer products on the FP32 matrix cores).
+// y = h_{L-1} W_L^T + b_L, h_l = relu(h_{l-1} W_l^T + b_l), loss =
 // mean (y - target)^2, Adam (Kingma & Ba, arXiv:1412.6980, Algorithm 1).
 // Weights start U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a counter-based
 // SplitMix64 stream (Steele, Lea & Flood, OOPSLA 2014); the last layer starts
@@ -34,18 +35,24 @@ struct SArgs {
   int64_t smm;
 };
 
-// C = alpha A B (+ beta C) (+ bias) (relu) (* mask): 64 x 64 tiles, 4 x 4 per lane.
+// C = alpha A B (+ beta C) (+ bias) (relu) (* mask) on the FP32 matrix cores:
+// 64 x 64 tiles, four waves (2 x 2) of 32 x 32, each 2 x 2 blocks of
+// v_mfma_f32_16x16x4f32.  K is walked in slices of 16 staged k-major in LDS
+// (As[k][m], Bs[k][n]), so a fragment read is one float per lane: lane l takes
+// A(m0 + l % 16, k + l / 16) and B(k + l / 16, n0 + l % 16); the result
+// element (i, j) of a 16 x 16 block is register i % 4 of lane j + 16 (i / 4).
 __global__ __launch_bounds__(256) void sgemm_kernel(const SArgs a) {
   __shared__ float As[SK][ST + 1];
   __shared__ float Bs[SK][ST + 1];
-  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
   const int64_t tiles_n = (a.N + ST - 1) / ST;
   const int64_t m0 = (blockIdx.x / tiles_n) * ST, n0 = (blockIdx.x % tiles_n) * ST;
-  float acc[4][4];
+  f4_t acc[2][2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.f;
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
   const bool a_kc = a.sak == 1, b_nc = a.sbn == 1;
   for (int64_t k0 = 0; k0 < a.K; k0 += SK) {
 #pragma unroll
@@ -60,32 +67,36 @@ __global__ __launch_bounds__(256) void sgemm_kernel(const SArgs a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < SK; ++k) {
-      float x[4], y[4];
+    for (int ks = 0; ks < SK; ks += 4) {
+      float af[2], bfr[2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) x[r] = As[k][4 * ti + r];
+      for (int i = 0; i < 2; ++i) af[i] = As[ks + (lane >> 4)][wm * 32 + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) y[c] = Bs[k][tj + 16 * c];
+      for (int j = 0; j < 2; ++j) bfr[j] = Bs[ks + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(x[r], y[c], acc[r][c]);
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t gm = m0 + 4 * ti + r, gn = n0 + tj + 16 * c;
-      if (gm >= a.M || gn >= a.N) continue;
-      float v = a.alpha * acc[r][c];
-      if (a.beta != 0.f) v += a.beta * a.C[gm * a.scm + gn];
-      if (a.bias) v += a.bias[gn];
-      if (a.relu) v = fmaxf(v, 0.f);
-      if (a.mask && !(a.mask[gm * a.smm + gn] > 0.f)) v = 0.f;
-      a.C[gm * a.scm + gn] = v;
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int64_t gn = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (gm >= a.M || gn >= a.N) continue;
+        float v = a.alpha * acc[i][j][r];
+        if (a.beta != 0.f) v += a.beta * a.C[gm * a.scm + gn];
+        if (a.bias) v += a.bias[gn];
+        if (a.relu) v = fmaxf(v, 0.f);
+        if (a.mask && !(a.mask[gm * a.smm + gn] > 0.f)) v = 0.f;
+        a.C[gm * a.scm + gn] = v;
+      }
 }
 
 void sgemm(const SArgs& a, hipStream_t s) {
@@ -167,6 +178,60 @@ __global__ void copy_rows_kernel(const float* src, int64_t lds, int64_t n, int64
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / w, c = e % w;
     dst[r * ldd + c] = src[r * lds + c];
+  }
+}
+
+// Column statistics of the stored rows (one work-group per column, FP64 sums
+// in a fixed order): center != 0 gives mean and 1 / std (1 where the column is
+// constant), center == 0 gives 1 / rms kept as the scale rms itself (1 where
+// the column is zero).
+__global__ __launch_bounds__(256) void colstats_kernel(const float* x, int64_t n, int64_t w,
+                                                       int center, float* mu, float* sc) {
+  __shared__ double sh[256];
+  const int64_t c = blockIdx.x;
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) s += (double)x[r * w + c];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  const double mean = center ? sh[0] / (double)n : 0.0;
+  __syncthreads();
+  double q = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) {
+    const double d = (double)x[r * w + c] - mean;
+    q += d * d;
+  }
+  sh[threadIdx.x] = q;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double sd = sqrt(sh[0] / (double)n);
+    const bool flat = !(sd > 1e-30 * (1.0 + fabs(mean)));
+    if (center) {
+      mu[c] = (float)mean;
+      sc[c] = flat ? 1.0f : (float)(1.0 / sd);
+    } else {
+      sc[c] = flat ? 1.0f : (float)sd;
+    }
+  }
+}
+
+// x[r][c] = (x[r][c] - mu[c]) * inv[c]  (mu may be null), rows of stride ld
+__global__ void std_rows_kernel(float* x, int64_t ld, int64_t n, int64_t w, const float* mu,
+                                const float* inv, int divide) {
+  const int64_t total = n * w;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / w, c = e % w;
+    float v = x[r * ld + c];
+    if (mu) v -= mu[c];
+    x[r * ld + c] = divide ? v / inv[c] : v * inv[c];
   }
 }
 
@@ -285,16 +350,40 @@ void mlp_loss_grad_dev(cpppl_mlp* m, const float* x, const float* t, int64_t n, 
   }
 }
 
+void mlp_std_x_dev(cpppl_mlp* m, float* x, int64_t ldx, int64_t n, hipStream_t s) {
+  if (!m->standardized || n <= 0) return;
+  const int64_t in = m->sizes[0];
+  hipLaunchKernelGGL(std_rows_kernel, dim3(nblk(n * in)), dim3(256), 0, s, x, ldx, n, in,
+                     (const float*)m->x_mu, (const float*)m->x_inv, 0);
+  CPPPL_LAUNCH_CHECK("std_rows");
+}
+
+void mlp_unscale_y_dev(cpppl_mlp* m, float* y, int64_t ldy, int64_t n, hipStream_t s) {
+  if (!m->standardized || n <= 0) return;
+  const int64_t out = m->sizes[m->nl];
+  // y * y_sc (no centring, multiplying)
+  hipLaunchKernelGGL(std_rows_kernel, dim3(nblk(n * out)), dim3(256), 0, s, y, ldy, n, out,
+                     (const float*)nullptr, (const float*)m->y_sc, 0);
+  CPPPL_LAUNCH_CHECK("unscale_rows");
+}
+
 void mlp_append_dev(cpppl_mlp* m, const float* x, int64_t ldx, const float* y, int64_t ldy,
                     int64_t n, hipStream_t s) {
   if (m->nrows + n > m->cap) throw std::invalid_argument("training set capacity exceeded");
   const int64_t in = m->sizes[0], out = m->sizes[m->nl];
-  hipLaunchKernelGGL(copy_rows_kernel, dim3(nblk(n * in)), dim3(256), 0, s, x, ldx, n, in,
-                     m->xs + m->nrows * in, in);
+  float* xd = m->xs + m->nrows * in;
+  float* yd = m->ys + m->nrows * out;
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(nblk(n * in)), dim3(256), 0, s, x, ldx, n, in, xd, in);
   CPPPL_LAUNCH_CHECK("copy_rows");
-  hipLaunchKernelGGL(copy_rows_kernel, dim3(nblk(n * out)), dim3(256), 0, s, y, ldy, n, out,
-                     m->ys + m->nrows * out, out);
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(nblk(n * out)), dim3(256), 0, s, y, ldy, n, out, yd,
+                     out);
   CPPPL_LAUNCH_CHECK("copy_rows");
+  if (m->standardized) {
+    mlp_std_x_dev(m, xd, in, n, s);
+    hipLaunchKernelGGL(std_rows_kernel, dim3(nblk(n * out)), dim3(256), 0, s, yd, out, n, out,
+                       (const float*)nullptr, (const float*)m->y_sc, 1);
+    CPPPL_LAUNCH_CHECK("std_rows");
+  }
   m->nrows += n;
 }
 
@@ -324,7 +413,8 @@ using namespace cpppl;
 
 static void mlp_free(cpppl_mlp* m) {
   for (void* p : {(void*)m->params, (void*)m->grads, (void*)m->adam_m, (void*)m->adam_v,
-                  (void*)m->xs, (void*)m->ys, (void*)m->work, (void*)m->scal})
+                  (void*)m->xs, (void*)m->ys, (void*)m->work, (void*)m->scal, (void*)m->x_mu,
+                  (void*)m->x_inv, (void*)m->y_sc})
     if (p) (void)hipFree(p);
   if (m->host_scal) (void)hipHostFree(m->host_scal);
 }
@@ -366,6 +456,9 @@ CPPPL_API cpppl_status cpppl_mlp_create(int in_dim, int hidden, int n_hidden, in
     CPPPL_HIP(hipMalloc((void**)&m->xs, (size_t)std::max<int64_t>(1, capacity * in_dim) * 4));
     CPPPL_HIP(hipMalloc((void**)&m->ys, (size_t)std::max<int64_t>(1, capacity * out_dim) * 4));
     CPPPL_HIP(hipMalloc((void**)&m->scal, 1024 * 4));
+    CPPPL_HIP(hipMalloc((void**)&m->x_mu, (size_t)in_dim * 4));
+    CPPPL_HIP(hipMalloc((void**)&m->x_inv, (size_t)in_dim * 4));
+    CPPPL_HIP(hipMalloc((void**)&m->y_sc, (size_t)out_dim * 4));
     CPPPL_HIP(hipHostMalloc((void**)&m->host_scal, 64 * 4, hipHostMallocDefault));
     std::vector<float> h((size_t)m->nparams, 0.f);
     for (int l = 1; l <= m->nl; ++l) {
@@ -551,6 +644,37 @@ CPPPL_API cpppl_status cpppl_mlp_train(cpppl_mlp* m, int epochs, float lr, int64
   MLP_CATCH(m)
 }
 
+CPPPL_API cpppl_status cpppl_mlp_standardize(cpppl_mlp* m) {
+  MLP_TRY(m)
+  if (m->standardized) throw std::logic_error("the network is already standardised");
+  if (m->nrows < 2) throw std::invalid_argument("standardising needs at least two stored rows");
+  const int64_t in = m->sizes[0], out = m->sizes[m->nl], n = m->nrows;
+  hipLaunchKernelGGL(colstats_kernel, dim3((unsigned)in), dim3(256), 0, nullptr, m->xs, n, in, 1,
+                     m->x_mu, m->x_inv);
+  CPPPL_LAUNCH_CHECK("colstats_x");
+  hipLaunchKernelGGL(colstats_kernel, dim3((unsigned)out), dim3(256), 0, nullptr, m->ys, n, out, 0,
+                     (float*)nullptr, m->y_sc);
+  CPPPL_LAUNCH_CHECK("colstats_y");
+  m->standardized = true;
+  mlp_std_x_dev(m, m->xs, in, n, nullptr);
+  hipLaunchKernelGGL(std_rows_kernel, dim3(nblk(n * out)), dim3(256), 0, nullptr, m->ys, out, n,
+                     out, (const float*)nullptr, (const float*)m->y_sc, 1);
+  CPPPL_LAUNCH_CHECK("std_rows");
+  CPPPL_HIP(hipDeviceSynchronize());
+  MLP_CATCH(m)
+}
+
+CPPPL_API cpppl_status cpppl_mlp_get_standardization(cpppl_mlp* m, float* x_mu, float* x_inv,
+                                                     float* y_sc) {
+  MLP_TRY(m)
+  if (!m->standardized) throw std::logic_error("the network is not standardised");
+  const int64_t in = m->sizes[0], out = m->sizes[m->nl];
+  if (x_mu) CPPPL_HIP(hipMemcpy(x_mu, m->x_mu, (size_t)in * 4, hipMemcpyDeviceToHost));
+  if (x_inv) CPPPL_HIP(hipMemcpy(x_inv, m->x_inv, (size_t)in * 4, hipMemcpyDeviceToHost));
+  if (y_sc) CPPPL_HIP(hipMemcpy(y_sc, m->y_sc, (size_t)out * 4, hipMemcpyDeviceToHost));
+  MLP_CATCH(m)
+}
+
 CPPPL_API cpppl_status cpppl_mlp_save(cpppl_mlp* m, const char* path) {
   MLP_TRY(m)
   if (!path) throw std::invalid_argument("path is NULL");
@@ -566,6 +690,17 @@ CPPPL_API cpppl_status cpppl_mlp_save(cpppl_mlp* m, const char* path) {
     ok = ok && fwrite(&v, 4, 1, f) == 1;
   }
   ok = ok && fwrite(h.data(), 4, h.size(), f) == h.size();
+  // the standardisation: a flag, then x_mu, x_inv (in_dim) and y_sc (out_dim)
+  const int64_t in = m->sizes[0], out = m->sizes[m->nl];
+  const int32_t sflag = m->standardized ? 1 : 0;
+  ok = ok && fwrite(&sflag, 4, 1, f) == 1;
+  if (m->standardized) {
+    std::vector<float> st((size_t)(2 * in + out));
+    CPPPL_HIP(hipMemcpy(st.data(), m->x_mu, (size_t)in * 4, hipMemcpyDeviceToHost));
+    CPPPL_HIP(hipMemcpy(st.data() + in, m->x_inv, (size_t)in * 4, hipMemcpyDeviceToHost));
+    CPPPL_HIP(hipMemcpy(st.data() + 2 * in, m->y_sc, (size_t)out * 4, hipMemcpyDeviceToHost));
+    ok = ok && fwrite(st.data(), 4, st.size(), f) == st.size();
+  }
   fclose(f);
   if (!ok) throw std::invalid_argument("write failed");
   MLP_CATCH(m)
@@ -586,9 +721,20 @@ CPPPL_API cpppl_status cpppl_mlp_load(cpppl_mlp* m, const char* path) {
   }
   std::vector<float> h((size_t)m->nparams);
   ok = ok && fread(h.data(), 4, h.size(), f) == h.size();
+  const int64_t in = m->sizes[0], out = m->sizes[m->nl];
+  int32_t sflag = 0;
+  ok = ok && fread(&sflag, 4, 1, f) == 1 && (sflag == 0 || sflag == 1);
+  std::vector<float> st((size_t)(2 * in + out));
+  if (ok && sflag) ok = fread(st.data(), 4, st.size(), f) == st.size();
   fclose(f);
   if (!ok) throw std::invalid_argument("file does not hold a network of this shape");
   CPPPL_HIP(hipMemcpy(m->params, h.data(), (size_t)m->nparams * 4, hipMemcpyHostToDevice));
+  if (sflag) {
+    CPPPL_HIP(hipMemcpy(m->x_mu, st.data(), (size_t)in * 4, hipMemcpyHostToDevice));
+    CPPPL_HIP(hipMemcpy(m->x_inv, st.data() + in, (size_t)in * 4, hipMemcpyHostToDevice));
+    CPPPL_HIP(hipMemcpy(m->y_sc, st.data() + 2 * in, (size_t)out * 4, hipMemcpyHostToDevice));
+  }
+  m->standardized = sflag != 0;
   MLP_CATCH(m)
 }
 

@@ -7,11 +7,14 @@
 //    dR (the chain evaluated on dt) at the previous factors, solved with the
 //    previous W, gives the first-order change of each factor column
 //    D_m = M_m(dR) W_m^{-1} / lambda;
-//  * learned: a per-column network maps [previous columns, D columns] of the
-//    four factors to a correction of the previous columns.
-// Features and targets are scaled by s = 1 / rms(D) so the network sees O(1)
-// numbers whatever the size of the step.  A candidate replaces the plain warm
-// start only if it has the lower ||CP||^2 - 2 <R, CP> for the new t.
+//  * learned: a per-column network maps [previous columns, D columns, log10 of
+//    the relative step ||dt|| / ||t||] of the four factors to a correction of
+//    the previous columns.
+// Features and targets are stored raw; cpppl_mlp_standardize fits per-column
+// centring and scaling on the stored rows (so the network sees O(1) numbers
+// whatever the step and mode sizes), and the learned candidate applies it on
+// the way in and undoes it on the way out.  A candidate replaces the plain
+// warm start only if it has the lower ||CP||^2 - 2 <R, CP> for the new t.
 #include <cmath>
 #include <limits>
 #include <stdexcept>
@@ -50,11 +53,18 @@ __global__ __launch_bounds__(TPB) void sumsq_kernel(const double* x, int64_t n, 
   if (threadIdx.x == 0) acc[0] += sh[0];
 }
 
-// scale[0] = 1 / sqrt(acc / count), or 1 if that is not a finite positive number
-__global__ void finish_scale_kernel(const double* acc, double count, double* scale) {
-  const double ms = acc[0] / count;
-  const double s = 1.0 / sqrt(ms);
-  scale[0] = (ms > 0.0 && isfinite(s)) ? s : 1.0;
+// out[0] = log10(sqrt(acc[0] / acc[1])), the relative step size; -30 for a zero step
+__global__ void log_ratio_kernel(const double* acc, double* out) {
+  const double r = sqrt(acc[0] / acc[1]);
+  out[0] = (r > 0.0 && isfinite(r)) ? log10(r) : -30.0;
+}
+
+// y[r][col] = (float)value[0] for every row r
+__global__ void fill_col_kernel(float* y, int64_t R, int64_t ldy, int64_t col, const double* value) {
+  const float v = (float)value[0];
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < R;
+       r += (int64_t)gridDim.x * blockDim.x)
+    y[r * ldy + col] = v;
 }
 
 // y[r][off + i] = (float)(x[r][i] * (scale ? *scale : 1))
@@ -66,38 +76,26 @@ __global__ void pack_kernel(const double* x, int64_t R, int64_t n, const double*
     y[(e / n) * ldy + off + e % n] = (float)(x[e] * s);
 }
 
-// F[r][i] = F0[r][i] + (D ? D[r][i] : 0) + (Y ? Y[r][off + i] / scale : 0)
+// F[r][i] = F0[r][i] + (D ? D[r][i] : 0) + (Y ? Y[r][off + i] : 0)
 __global__ void candidate_kernel(const double* F0, const double* D, const float* Y, int64_t ldy,
-                                 int64_t off, const double* scale, int64_t R, int64_t n,
-                                 double* F) {
-  const double inv = scale ? 1.0 / scale[0] : 1.0;
+                                 int64_t off, int64_t R, int64_t n, double* F) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R * n;
        e += (int64_t)gridDim.x * blockDim.x) {
     double v = F0[e];
     if (D) v += D[e];
-    if (Y) v += (double)Y[(e / n) * ldy + off + e % n] * inv;
+    if (Y) v += (double)Y[(e / n) * ldy + off + e % n];
     F[e] = v;
   }
 }
 
-// y[r][off + i] *= scale, as float
-__global__ void scale_cols_kernel(float* y, int64_t R, int64_t ldy, int64_t off, int64_t n,
-                                  const double* scale) {
-  const float s = (float)scale[0];
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R * n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    y[(e / n) * ldy + off + e % n] *= s;
-}
-
-void set_candidate(cpppl_ctx* c, const double* const D[4], const float* Y, int64_t ldy,
-                   const double* scale) {
+void set_candidate(cpppl_ctx* c, const double* const D[4], const float* Y, int64_t ldy) {
   const Plan& p = c->plan;
   const int64_t R = c->d.rank;
   int64_t off = 0;
   for (int m = 0; m < 4; ++m) {
     const int64_t n = ws_nmode(c->d, m);
     hipLaunchKernelGGL(candidate_kernel, dim3(nb(R * n)), dim3(TPB), 0, c->stream,
-                       c->at<double>(p.wsF[m]), D ? D[m] : nullptr, Y, ldy, off, scale, R, n,
+                       c->at<double>(p.wsF[m]), D ? D[m] : nullptr, Y, ldy, off, R, n,
                        c->at<double>(p.FT[m]));
     CPPPL_LAUNCH_CHECK("candidate");
     off += n;
@@ -137,7 +135,7 @@ void set_candidate(cpppl_ctx* c, const double* const D[4], const float* Y, int64
 
 extern "C" {
 
-CPPPL_API int64_t cpppl_ws_in_dim(const cpppl_dims* d) { return d ? 2 * (2 * d->o + 2 * d->v) : 0; }
+CPPPL_API int64_t cpppl_ws_in_dim(const cpppl_dims* d) { return d ? 2 * (2 * d->o + 2 * d->v) + 1 : 0; }
 CPPPL_API int64_t cpppl_ws_out_dim(const cpppl_dims* d) { return d ? (2 * d->o + 2 * d->v) : 0; }
 
 CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* c, const double* dt, int on_device,
@@ -176,7 +174,6 @@ CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* c, const double* dt, int on_d
 
   // first-order change from the MTTKRP of dR at the previous factors
   ws_load_dt(c, dt, on_device);
-  zero_doubles(sc + S_WS_SUMSQ, 1, c->stream);
   for (int m = 0; m < 4; ++m) {
     const int64_t n = ws_nmode(c->d, m);
     ws_mttkrp_dt(c, m);
@@ -184,15 +181,20 @@ CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* c, const double* dt, int on_d
     hipLaunchKernelGGL(div_rows_kernel, dim3(nb(R * n)), dim3(TPB), 0, c->stream,
                        c->at<double>(p.wsD[m]), c->at<double>(p.wsLam), R, n);
     CPPPL_LAUNCH_CHECK("div_rows");
-    hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(TPB), 0, c->stream, c->at<double>(p.wsD[m]),
-                       R * n, sc + S_WS_SUMSQ);
-    CPPPL_LAUNCH_CHECK("sumsq");
   }
-  hipLaunchKernelGGL(finish_scale_kernel, dim3(1), dim3(1), 0, c->stream, sc + S_WS_SUMSQ,
-                     (double)(R * out_dim), sc + S_WS_SCALE);
-  CPPPL_LAUNCH_CHECK("finish_scale");
+  // the relative step size ||dt|| / ||t|| (t before the step), as log10
+  const int64_t nt = c->d.o * c->d.o * c->d.v * c->d.v;
+  zero_doubles(sc + S_WS_SUMSQ, 2, c->stream);
+  hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(TPB), 0, c->stream, c->at<double>(p.dt64), nt,
+                     sc + S_WS_SUMSQ);
+  hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(TPB), 0, c->stream, ws_t_doubles(c), nt,
+                     sc + S_WS_SUMSQ + 1);
+  CPPPL_LAUNCH_CHECK("sumsq");
+  hipLaunchKernelGGL(log_ratio_kernel, dim3(1), dim3(1), 0, c->stream, sc + S_WS_SUMSQ,
+                     sc + S_WS_SCALE);
+  CPPPL_LAUNCH_CHECK("log_ratio");
 
-  // features [F_gamma, F_rho, F_alpha, F_beta, s D_gamma, s D_rho, s D_alpha, s D_beta]
+  // features [F_gamma, F_rho, F_alpha, F_beta, D_gamma, D_rho, D_alpha, D_beta, log10 step]
   float* feat = c->at<float>(p.wsFeat);
   int64_t off = 0;
   for (int m = 0; m < 4; ++m) {
@@ -200,12 +202,24 @@ CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* c, const double* dt, int on_d
     hipLaunchKernelGGL(pack_kernel, dim3(nb(R * n)), dim3(TPB), 0, c->stream,
                        c->at<double>(p.wsF[m]), R, n, (const double*)nullptr, feat, in_dim, off);
     hipLaunchKernelGGL(pack_kernel, dim3(nb(R * n)), dim3(TPB), 0, c->stream,
-                       c->at<double>(p.wsD[m]), R, n, (const double*)(sc + S_WS_SCALE), feat, in_dim,
+                       c->at<double>(p.wsD[m]), R, n, (const double*)nullptr, feat, in_dim,
                        out_dim + off);
     CPPPL_LAUNCH_CHECK("pack");
     off += n;
   }
-  if (strategy == CPPPL_WS_LEARNED) mlp_forward_dev(mlp, feat, R, c->at<float>(p.wsOut), c->stream);
+  hipLaunchKernelGGL(fill_col_kernel, dim3(nb(R)), dim3(TPB), 0, c->stream, feat, R, in_dim,
+                     in_dim - 1, (const double*)(sc + S_WS_SCALE));
+  CPPPL_LAUNCH_CHECK("fill_col");
+  if (strategy == CPPPL_WS_LEARNED) {
+    // the network sees the features standardised as its training rows were,
+    // on a copy (the raw features stay for cpppl_ws_training_rows)
+    float* xin = c->at<float>(p.wsFeatStd);
+    CPPPL_HIP(hipMemcpyAsync(xin, feat, (size_t)(R * in_dim) * 4, hipMemcpyDeviceToDevice,
+                             c->stream));
+    mlp_std_x_dev(mlp, xin, in_dim, R, c->stream);
+    mlp_forward_dev(mlp, xin, R, c->at<float>(p.wsOut), c->stream);
+    mlp_unscale_y_dev(mlp, c->at<float>(p.wsOut), out_dim, R, c->stream);
+  }
 
   // the new amplitudes: t <- t + dt
   ws_add_dt(c);
@@ -218,12 +232,12 @@ CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* c, const double* dt, int on_d
     const double* D[4];
     for (int m = 0; m < 4; ++m) D[m] = c->at<double>(p.wsD[m]);
     if (strategy == CPPPL_WS_FIRST_ORDER)
-      set_candidate(c, D, nullptr, 0, nullptr);
+      set_candidate(c, D, nullptr, 0);
     else
-      set_candidate(c, nullptr, c->at<float>(p.wsOut), out_dim, sc + S_WS_SCALE);
+      set_candidate(c, nullptr, c->at<float>(p.wsOut), out_dim);
     const double l_cand = ws_judge_loss(c);
     if (std::isfinite(l_cand) && l_cand < l_plain) pick = strategy;
-    else set_candidate(c, nullptr, nullptr, 0, nullptr);
+    else set_candidate(c, nullptr, nullptr, 0);
   }
   c->ws_valid = true;
   ws_sync(c);
@@ -242,13 +256,10 @@ CPPPL_API cpppl_status cpppl_ws_training_rows(cpppl_ctx* c, cpppl_mlp* mlp) {
   const int64_t R = c->d.rank;
   float* y = c->at<float>(p.wsOut);
   int64_t off = 0;
-  for (int m = 0; m < 4; ++m) {  // target = s (aligned converged column - previous column)
+  for (int m = 0; m < 4; ++m) {  // target = aligned converged column - previous column
     const int64_t n = ws_nmode(c->d, m);
     aligned_delta_f32(c->at<double>(p.FT[m]), c->at<double>(p.wsF[m]), R, n, y + off, out_dim,
                       c->stream);
-    hipLaunchKernelGGL(scale_cols_kernel, dim3(nb(R * n)), dim3(TPB), 0, c->stream, y, R, out_dim,
-                       off, n, (const double*)(c->at<double>(p.scal) + S_WS_SCALE));
-    CPPPL_LAUNCH_CHECK("scale_cols");
     off += n;
   }
   mlp_append_dev(mlp, c->at<float>(p.wsFeat), in_dim, y, out_dim, R, c->stream);

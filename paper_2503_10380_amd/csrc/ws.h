@@ -27,6 +27,8 @@ void ws_ensure_norm(cpppl_ctx* c);
 bool ws_install_near_cache(cpppl_ctx* c);
 void ws_copy(cpppl_ctx* c, size_t dst, size_t src, size_t bytes);
 void ws_sync(cpppl_ctx* c);
+// The doubles amplitudes (the raw t2 when a singles dressing is on).
+const double* ws_t_doubles(cpppl_ctx* c);
 int64_t ws_nmode(const cpppl_dims& d, int m);
 // MTTKRP of `mode` with dt (loaded by ws_load_dt) in place of t, into MT.
 void ws_mttkrp_dt(cpppl_ctx* c, int mode);

@@ -74,7 +74,7 @@ def test_status_strings_and_null_handling(lib):
     assert lib.cpppl_destroy(None) == -1
     assert lib.cpppl_als(None, None, None) == -1
     d = cp.Dims(4, 16, 48, 32)
-    assert lib.cpppl_ws_in_dim(C.byref(d)) == 2 * (2 * 4 + 2 * 16)
+    assert lib.cpppl_ws_in_dim(C.byref(d)) == 2 * (2 * 4 + 2 * 16) + 1
     assert lib.cpppl_ws_out_dim(C.byref(d)) == 2 * 4 + 2 * 16
 
 

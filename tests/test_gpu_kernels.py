@@ -256,3 +256,4 @@ def test_spd_inverse_flags_indefinite(env):
                                 status.data_ptr(), torch.cuda.current_stream().cuda_stream)
     assert st == 0 and int(status[0]) == 1
     assert torch.isfinite(ty).all()
+
