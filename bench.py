@@ -145,6 +145,41 @@ def digest_counters(fetch_csv, write_csv, steps, calib_mib, out_path):
     print(json.dumps(out, indent=1))
 
 
+def digest_mfma(csv_path, steps, out_path, n_cu=256):
+    """Matrix-core busy fraction per MTTKRP kernel class from one rocprofv3
+    --pmc run of SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE (per dispatch) of
+    `bench.py --steps S --warmup W --no-cpu --no-compare`: for the last S
+    sweeps' BF16 GEMM dispatches (labelled by the fixed issue order as in
+    digest_counters), busy = sum MFMA_BUSY / (n_cu * sum GUI_ACTIVE)."""
+    import csv
+    rows = sorted(csv.DictReader(open(csv_path)), key=lambda r: int(r["Dispatch_Id"]))
+    per = {}
+    for r in rows:
+        d = per.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    disp = [per[k] for k in sorted(per)]
+    idx = [i for i, d in enumerate(disp) if d["name"].startswith("gemm_bf16_kernel")]
+    per_sweep = sum(LAUNCHES[c] for c in SWEEP_GEMMS)
+    idx = idx[-per_sweep * steps:]
+    acc = {}
+    pos = 0
+    for _ in range(steps):
+        for cls in SWEEP_GEMMS:
+            for i in idx[pos:pos + LAUNCHES[cls]]:
+                a = acc.setdefault(cls, [0.0, 0.0, 0])
+                a[0] += disp[i].get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+                a[1] += disp[i].get("GRBM_GUI_ACTIVE", 0.0)
+                a[2] += 1
+            pos += LAUNCHES[cls]
+    out = {"n_cu": n_cu, "classes": {c: {"mfma_busy_cycles": a[0], "gui_active_cycles": a[1],
+                                          "launches": a[2],
+                                          "mfma_busy_frac": a[0] / (n_cu * a[1]) if a[1] else None}
+                                      for c, a in acc.items()}}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def roofline_for(cls, flops, nbytes, launch_ms):
     """Roofline of one kernel class: bound by whichever of dense-BF16 MFMA time
     and HBM time is larger for its algorithmic flops and bytes."""
@@ -224,6 +259,33 @@ def cpu_baseline(cfg, inp, fs, occ=8):
         "r_formation_s_extrapolated": t_form * scale,
         "sample_wall_s": t_form + t_sweep,
     }
+
+
+def cpu_oracle_runs(args):
+    """The FP64 oracle run whole on the host cores (the CPU baseline of the
+    small workloads): C1 (R formed, 50 sweeps) and C2 (R formed, 30 sweeps),
+    from the seeded random start."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    out = {"cores": int(threads), "cpu_count": os.cpu_count(), "kind": "oracle", "runs": {}}
+    for name in ("C1", "C2"):
+        cfg = synth.CONFIGS[name]
+        inp = synth.make_inputs(cfg)
+        fs = synth.init_factors(cfg)
+        t0 = time.perf_counter()
+        r = oracle.form_r(inp.t, inp.b_vv)
+        t_form = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, _, hist = oracle.cp_als(r, fs, cfg.sweeps, norm_r2=float(np.sum(r * r)))
+        t_als = time.perf_counter() - t0
+        out["runs"][name] = {"r_formation_s": t_form, "sweeps": cfg.sweeps, "als_s": t_als,
+                             "sweeps_per_s": cfg.sweeps / t_als, "fit": hist["fit"][-1]}
+        print(f"cpu oracle {name}: {json.dumps(out['runs'][name])}", file=sys.stderr, flush=True)
+    return out
 
 
 def time_to_fit(cp, torch, cfg, inp, fs, dev_t, dev_b, args):
@@ -510,7 +572,9 @@ def warmstart_experiment(cp, torch, args):
         train_sweeps.append(r["sweeps"])
         ctx.training_rows(net)
         state = ctx.get_factors()
+        print(f"warmstart: training step {k}: {r['sweeps']} sweeps", file=sys.stderr, flush=True)
     t_train = time.perf_counter()
+    net.standardize()
     hist = net.train(args.ws_epochs, lr=1e-3, batch=512, seed=1)
     t_train = time.perf_counter() - t_train
     rows = []
@@ -541,6 +605,9 @@ def warmstart_experiment(cp, torch, args):
                          "loss_gap0": float((n2 - 2 * inner0 + cp20 - res2_star) / res2_star),
                          "sweeps_to_1e-4": n, "wall_s_to_1e-4": wall, "warm_start_s": ws_s}
         rows.append(row)
+        print(f"warmstart: evaluation step {k}: " + ", ".join(
+            f"{name} chosen {row[name]['chosen']} gap {row[name]['loss_gap0']:.3e}"
+            for name, _ in strategies), file=sys.stderr, flush=True)
     summary = {}
     for name, _ in strategies:
         ns = [r[name]["sweeps_to_1e-4"] for r in rows]
@@ -560,7 +627,8 @@ def warmstart_experiment(cp, torch, args):
             "step0": {"sweeps": r0["sweeps"], "fit": r0["fit"]},
             "train": {"steps": 10, "sweeps_per_step": train_sweeps, "rows": net.num_rows,
                       "epochs": args.ws_epochs, "loss_first": float(hist[0]),
-                      "loss_last": float(hist[-1]), "train_s": t_train},
+                      "loss_last": float(hist[-1]), "loss_ratio": float(hist[0] / hist[-1]),
+                      "train_s": t_train, "standardized": True},
             "summary": summary, "steps": rows,
             "wall_s": time.perf_counter() - t0}
 
@@ -646,7 +714,7 @@ def main():
     ap.add_argument("--ccd-tol", type=float, default=1e-3,
                     help="ccd: ALS stop |dfit| < tol per CC step (the paper's 1e-3)")
     ap.add_argument("--ccd-cap", type=int, default=100)
-    ap.add_argument("--experiment", choices=["warmstart", "precision", "ccd"],
+    ap.add_argument("--experiment", choices=["warmstart", "precision", "ccd", "cpu"],
                     help="warmstart: the learned warm-start experiment (C4 unless --config); "
                          "precision: the FP64 / BF16 / FP8 ablation (C5 unless --config)")
     ap.add_argument("--ws-epochs", type=int, default=300)
@@ -657,6 +725,9 @@ def main():
     ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
                          "script into profiles/traffic_counters.json and exit")
+    ap.add_argument("--digest-mfma", metavar="CSV",
+                    help="summarise a rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE "
+                         "run of this script into profiles/mfma_busy_c3.json and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run three plain device copies of MIB MiB each, so that "
                          "HBM byte counters can be scaled against a kernel of known traffic")
@@ -666,6 +737,9 @@ def main():
         import paper_2503_10380_amd as cp
         args.config = args.config or "C4"
         print(json.dumps(warmstart_experiment(cp, torch, args)))
+        return
+    if args.experiment == "cpu":
+        print(json.dumps(cpu_oracle_runs(args)))
         return
     if args.experiment == "ccd":
         import torch
@@ -678,6 +752,9 @@ def main():
         import paper_2503_10380_amd as cp
         args.config = args.config or "C5"
         print(json.dumps(precision_ablation(cp, torch, args)))
+        return
+    if args.digest_mfma:
+        digest_mfma(args.digest_mfma, args.steps, os.path.join(ROOT, "profiles", "mfma_busy_c3.json"))
         return
     if args.digest_counters:
         digest_counters(args.digest_counters[0], args.digest_counters[1], args.steps,

@@ -308,7 +308,8 @@ CPPPL_API cpppl_status cpppl_mlp_load(cpppl_mlp* mlp, const char* path);
 /* Warm-start strategies. */
 enum {
   CPPPL_WS_PLAIN = 0,       /* previous converged factors (the paper's "optimal guess") */
-  CPPPL_WS_LEARNED = 1,     /* previous factors + network correction, judged against PLAIN */
+  CPPPL_WS_LEARNED = 1,     /* previous factors + first-order change + network correction,
+                               judged against PLAIN and FIRST_ORDER */
   CPPPL_WS_FIRST_ORDER = 2, /* previous factors + first-order ALS change from dR (no network) */
   CPPPL_WS_NEAR_OPTIMAL = 3 /* the near-optimal cache (see cpppl_als_opts.near_cache); PLAIN
                                while no cache exists.  No features are formed. */
@@ -323,17 +324,18 @@ CPPPL_API int64_t cpppl_ws_out_dim(const cpppl_dims* dims);
  * (previous converged) factors, forms per-column features [F, D, log10
  * (||dt|| / ||t||)] with D = dR-MTTKRP W^-1 / lambda the first-order change
  * of each factor column (modes i, j, a, b), then sets t <- t + dt and the
- * factors to the chosen candidate.  For LEARNED the candidate is F + the
- * network's correction (through the network's standardisation, see
- * cpppl_mlp_standardize); for LEARNED and FIRST_ORDER the candidate replaces
- * PLAIN only if its ||CP||^2 - 2 <R, CP> (R of the new t) is lower; *chosen
- * reports the start kept (a CPPPL_WS_* value).  The raw features are kept for
- * cpppl_ws_training_rows.  mlp may be NULL unless strategy is LEARNED. */
+ * factors to the chosen candidate.  FIRST_ORDER forms F + D; LEARNED forms
+ * F + D and F + D + the network's correction (through the network's
+ * standardisation, see cpppl_mlp_standardize).  The judge keeps, of PLAIN and
+ * the candidates formed, the one with the lowest ||CP||^2 - 2 <R, CP> (R of
+ * the new t); *chosen reports it (a CPPPL_WS_* value).  The raw features are
+ * kept for cpppl_ws_training_rows.  mlp may be NULL unless strategy is LEARNED. */
 CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* ctx, const double* dt, int on_device,
                                         int strategy, cpppl_mlp* mlp, int* chosen);
 /* After ALS from a warm start: write the R training rows of that step (the
  * raw features of the warm start, and targets = the current (converged)
- * minus the previous factors, per column, sign-aligned) into the network's
+ * minus the previous factors, per column, sign-aligned, minus the first-order
+ * change D: what the first-order candidate misses) into the network's
  * training set (standardised on the way in if the network is). */
 CPPPL_API cpppl_status cpppl_ws_training_rows(cpppl_ctx* ctx, cpppl_mlp* mlp);
 

@@ -7,14 +7,17 @@
 //    dR (the chain evaluated on dt) at the previous factors, solved with the
 //    previous W, gives the first-order change of each factor column
 //    D_m = M_m(dR) W_m^{-1} / lambda;
-//  * learned: a per-column network maps [previous columns, D columns, log10 of
-//    the relative step ||dt|| / ||t||] of the four factors to a correction of
-//    the previous columns.
+//  * learned: the first-order candidate plus a per-column network's correction:
+//    the network maps [previous columns, D columns, log10 of the relative step
+//    ||dt|| / ||t||] of the four factors to the part of the change of the
+//    columns that the first-order change misses (an untrained network leaves
+//    the first-order candidate).
 // Features and targets are stored raw; cpppl_mlp_standardize fits per-column
 // centring and scaling on the stored rows (so the network sees O(1) numbers
 // whatever the step and mode sizes), and the learned candidate applies it on
-// the way in and undoes it on the way out.  A candidate replaces the plain
-// warm start only if it has the lower ||CP||^2 - 2 <R, CP> for the new t.
+// the way in and undoes it on the way out.  The judge keeps, of the plain
+// warm start and the candidates formed, the one with the lowest
+// ||CP||^2 - 2 <R, CP> for the new t.
 #include <cmath>
 #include <limits>
 #include <stdexcept>
@@ -74,6 +77,14 @@ __global__ void pack_kernel(const double* x, int64_t R, int64_t n, const double*
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R * n;
        e += (int64_t)gridDim.x * blockDim.x)
     y[(e / n) * ldy + off + e % n] = (float)(x[e] * s);
+}
+
+// y[r][off + i] -= (float)D[r][i]
+__global__ void sub_rows_kernel(float* y, int64_t ldy, int64_t off, const double* D, int64_t R,
+                                int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R * n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[(e / n) * ldy + off + e % n] -= (float)D[e];
 }
 
 // F[r][i] = F0[r][i] + (D ? D[r][i] : 0) + (Y ? Y[r][off + i] : 0)
@@ -225,19 +236,29 @@ CPPPL_API cpppl_status cpppl_warm_start(cpppl_ctx* c, const double* dt, int on_d
   ws_add_dt(c);
   ws_derive_t(c);
 
-  // judge against the plain warm start
+  // the judge: the lowest ||CP||^2 - 2 <R, CP> at the new t among the plain
+  // start, the first-order candidate and (LEARNED) the network's
   int pick = CPPPL_WS_PLAIN;
   if (strategy != CPPPL_WS_PLAIN) {
-    const double l_plain = ws_judge_loss(c);  // factors are still the previous ones
+    double best = ws_judge_loss(c);  // factors are still the previous ones
     const double* D[4];
     for (int m = 0; m < 4; ++m) D[m] = c->at<double>(p.wsD[m]);
-    if (strategy == CPPPL_WS_FIRST_ORDER)
-      set_candidate(c, D, nullptr, 0);
-    else
-      set_candidate(c, nullptr, c->at<float>(p.wsOut), out_dim);
-    const double l_cand = ws_judge_loss(c);
-    if (std::isfinite(l_cand) && l_cand < l_plain) pick = strategy;
-    else set_candidate(c, nullptr, nullptr, 0);
+    set_candidate(c, D, nullptr, 0);
+    const double l_fo = ws_judge_loss(c);
+    if (std::isfinite(l_fo) && l_fo < best) {
+      best = l_fo;
+      pick = CPPPL_WS_FIRST_ORDER;
+    }
+    if (strategy == CPPPL_WS_LEARNED) {
+      set_candidate(c, D, c->at<float>(p.wsOut), out_dim);
+      const double l_learn = ws_judge_loss(c);
+      if (std::isfinite(l_learn) && l_learn < best) {
+        best = l_learn;
+        pick = CPPPL_WS_LEARNED;
+      }
+    }
+    if (pick == CPPPL_WS_PLAIN) set_candidate(c, nullptr, nullptr, 0);
+    else if (pick == CPPPL_WS_FIRST_ORDER && strategy == CPPPL_WS_LEARNED) set_candidate(c, D, nullptr, 0);
   }
   c->ws_valid = true;
   ws_sync(c);
@@ -256,10 +277,14 @@ CPPPL_API cpppl_status cpppl_ws_training_rows(cpppl_ctx* c, cpppl_mlp* mlp) {
   const int64_t R = c->d.rank;
   float* y = c->at<float>(p.wsOut);
   int64_t off = 0;
-  for (int m = 0; m < 4; ++m) {  // target = aligned converged column - previous column
+  // target = aligned converged column - previous column - first-order change
+  for (int m = 0; m < 4; ++m) {
     const int64_t n = ws_nmode(c->d, m);
     aligned_delta_f32(c->at<double>(p.FT[m]), c->at<double>(p.wsF[m]), R, n, y + off, out_dim,
                       c->stream);
+    hipLaunchKernelGGL(sub_rows_kernel, dim3(nb(R * n)), dim3(TPB), 0, c->stream, y, out_dim, off,
+                       (const double*)c->at<double>(p.wsD[m]), R, n);
+    CPPPL_LAUNCH_CHECK("sub_rows");
     off += n;
   }
   mlp_append_dev(mlp, c->at<float>(p.wsFeat), in_dim, y, out_dim, R, c->stream);

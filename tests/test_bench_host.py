@@ -99,3 +99,33 @@ def test_dominant_class_breaks_near_ties_toward_the_weaker_kernel():
     assert bench.dominant_class(rep, rl) == "z"
     # per launch: a class call of y is LAUNCHES["y"] launches
     assert rl["y"]["avg_launch_ms"] == pytest.approx(11.0 / (40 * bench.LAUNCHES["y"]))
+
+
+def test_digest_mfma_groups_launches(tmp_path):
+    """Two counters per dispatch (one CSV row each): a warm-up sweep is ignored,
+    and each class's busy fraction is its summed MFMA-busy cycles over CUs x
+    its summed active cycles."""
+    busy = {c: 1000.0 * (i + 1) for i, c in enumerate(bench.CLASSES)}
+    path = tmp_path / "m.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        did = 0
+        for sweep in range(3):
+            for cls in bench.SWEEP_GEMMS:
+                for _ in range(bench.LAUNCHES[cls]):
+                    b = busy[cls] if sweep else 1e9
+                    w.writerow({"Dispatch_Id": did, "Kernel_Name": "gemm_bf16_kernel<...>",
+                                "Counter_Name": "SQ_VALU_MFMA_BUSY_CYCLES", "Counter_Value": b})
+                    w.writerow({"Dispatch_Id": did, "Kernel_Name": "gemm_bf16_kernel<...>",
+                                "Counter_Name": "GRBM_GUI_ACTIVE", "Counter_Value": 10.0})
+                    did += 1
+                w.writerow({"Dispatch_Id": did, "Kernel_Name": "fit_rows_kernel",
+                            "Counter_Name": "GRBM_GUI_ACTIVE", "Counter_Value": 5.0})
+                did += 1
+    out = tmp_path / "o.json"
+    bench.digest_mfma(str(path), 2, str(out), n_cu=4)
+    d = json.load(open(out))["classes"]
+    for cls in bench.CLASSES:
+        assert d[cls]["mfma_busy_frac"] == pytest.approx(busy[cls] / (4 * 10.0))
+        assert d[cls]["launches"] == 2 * bench.SWEEP_GEMMS.count(cls) * bench.LAUNCHES[cls]
