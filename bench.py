@@ -145,18 +145,26 @@ def digest_counters(fetch_csv, write_csv, steps, calib_mib, out_path):
     print(json.dumps(out, indent=1))
 
 
-def digest_mfma(csv_path, steps, out_path, n_cu=256):
-    """Matrix-core busy fraction per MTTKRP kernel class from one rocprofv3
-    --pmc run of SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE (per dispatch) of
+def digest_mfma(csv_path, steps, out_path, n_cu=256, simd_per_cu=4, n_xcd=8):
+    """Matrix-core utilisation per MTTKRP kernel class from one rocprofv3 --pmc
+    run of SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE (per dispatch) of
     `bench.py --steps S --warmup W --no-cpu --no-compare`: for the last S
     sweeps' BF16 GEMM dispatches (labelled by the fixed issue order as in
-    digest_counters), busy = sum MFMA_BUSY / (n_cu * sum GUI_ACTIVE)."""
+    digest_counters).  A 16x16x32 BF16 MFMA counts 16 busy cycles on its SIMD,
+    the rate at which 4 SIMDs x 256 CUs at 2.4 GHz give the 2.5 PFLOP/s dense
+    peak, and GRBM_GUI_ACTIVE adds the active cycles of the n_xcd dies, so
+        util = sum MFMA_BUSY / (simd_per_cu * n_cu * sum GUI_ACTIVE / n_xcd).
+    The dispatch timestamps give a second reading of the same fraction at the
+    nominal 2.4 GHz clock, and GUI_ACTIVE / n_xcd over the dispatch time gives
+    the clock it implies."""
     import csv
     rows = sorted(csv.DictReader(open(csv_path)), key=lambda r: int(r["Dispatch_Id"]))
     per = {}
     for r in rows:
         d = per.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})
         d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        if r.get("Start_Timestamp") and r.get("End_Timestamp"):
+            d["ns"] = float(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     disp = [per[k] for k in sorted(per)]
     idx = [i for i, d in enumerate(disp) if d["name"].startswith("gemm_bf16_kernel")]
     per_sweep = sum(LAUNCHES[c] for c in SWEEP_GEMMS)
@@ -166,15 +174,23 @@ def digest_mfma(csv_path, steps, out_path, n_cu=256):
     for _ in range(steps):
         for cls in SWEEP_GEMMS:
             for i in idx[pos:pos + LAUNCHES[cls]]:
-                a = acc.setdefault(cls, [0.0, 0.0, 0])
+                a = acc.setdefault(cls, [0.0, 0.0, 0, 0.0])
                 a[0] += disp[i].get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
                 a[1] += disp[i].get("GRBM_GUI_ACTIVE", 0.0)
                 a[2] += 1
+                a[3] += disp[i].get("ns", 0.0)
             pos += LAUNCHES[cls]
-    out = {"n_cu": n_cu, "classes": {c: {"mfma_busy_cycles": a[0], "gui_active_cycles": a[1],
-                                          "launches": a[2],
-                                          "mfma_busy_frac": a[0] / (n_cu * a[1]) if a[1] else None}
-                                      for c, a in acc.items()}}
+    lanes = simd_per_cu * n_cu
+    classes = {}
+    for c, (busy, gui, n, ns) in acc.items():
+        e = {"mfma_busy_cycles": busy, "gui_active_cycles": gui, "launches": n,
+             "mfma_util": busy / (lanes * gui / n_xcd) if gui else None}
+        if ns:
+            e["dispatch_ns"] = ns
+            e["mfma_util_at_2p4ghz"] = busy / (lanes * 2.4 * ns)
+            e["implied_clock_ghz"] = gui / n_xcd / ns
+        classes[c] = e
+    out = {"n_cu": n_cu, "simd_per_cu": simd_per_cu, "n_xcd": n_xcd, "classes": classes}
     with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))

@@ -103,8 +103,8 @@ def test_dominant_class_breaks_near_ties_toward_the_weaker_kernel():
 
 def test_digest_mfma_groups_launches(tmp_path):
     """Two counters per dispatch (one CSV row each): a warm-up sweep is ignored,
-    and each class's busy fraction is its summed MFMA-busy cycles over CUs x
-    its summed active cycles."""
+    and each class's utilisation is its summed MFMA-busy cycles over SIMDs x
+    its summed active cycles per die."""
     busy = {c: 1000.0 * (i + 1) for i, c in enumerate(bench.CLASSES)}
     path = tmp_path / "m.csv"
     with open(path, "w", newline="") as f:
@@ -124,8 +124,8 @@ def test_digest_mfma_groups_launches(tmp_path):
                             "Counter_Name": "GRBM_GUI_ACTIVE", "Counter_Value": 5.0})
                 did += 1
     out = tmp_path / "o.json"
-    bench.digest_mfma(str(path), 2, str(out), n_cu=4)
+    bench.digest_mfma(str(path), 2, str(out), n_cu=4, simd_per_cu=4, n_xcd=8)
     d = json.load(open(out))["classes"]
     for cls in bench.CLASSES:
-        assert d[cls]["mfma_busy_frac"] == pytest.approx(busy[cls] / (4 * 10.0))
+        assert d[cls]["mfma_util"] == pytest.approx(busy[cls] / (16 * 10.0 / 8))
         assert d[cls]["launches"] == 2 * bench.SWEEP_GEMMS.count(cls) * bench.LAUNCHES[cls]
