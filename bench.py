@@ -86,11 +86,11 @@ def traffic_for(kernel):
 
 
 # BF16 products of one ALS sweep in issue order (main stream).  While a
-# side-stream inverse is pending the library cuts each unsplit product into
-# four launches (split-K products stay whole), so a class call is LAUNCHES[cls]
-# consecutive gemm_bf16_kernel dispatches.
+# side-stream inverse is pending the library cuts tau and G into four launches
+# and Z into two (Y and the split-K products stay whole), so a class call is
+# LAUNCHES[cls] consecutive BF16 GEMM dispatches (kernels named gemm_bf16*).
 SWEEP_GEMMS = ["kr_t2", "z", "m", "y", "z", "m", "y", "g", "h"]
-LAUNCHES = {"kr_t2": 4, "y": 4, "z": 4, "g": 4, "m": 1, "h": 1}
+LAUNCHES = {"kr_t2": 4, "y": 1, "z": 2, "g": 4, "m": 1, "h": 1}
 
 
 def digest_counters(fetch_csv, write_csv, steps, calib_mib, out_path):
@@ -121,7 +121,7 @@ def digest_counters(fetch_csv, write_csv, steps, calib_mib, out_path):
         out["calibration"][name] = {"known_bytes": known, "counted_bytes": sum(big) / len(big),
                                     "factor": factor}
         per_sweep = sum(LAUNCHES[c] for c in SWEEP_GEMMS)
-        idx = [i for i, (k, _) in enumerate(d) if k.startswith("gemm_bf16_kernel")]
+        idx = [i for i, (k, _) in enumerate(d) if k.startswith("gemm_bf16")]
         idx = idx[-per_sweep * steps:]
         pos = 0
         for _ in range(steps):
@@ -166,7 +166,7 @@ def digest_mfma(csv_path, steps, out_path, n_cu=256, simd_per_cu=4, n_xcd=8):
         if r.get("Start_Timestamp") and r.get("End_Timestamp"):
             d["ns"] = float(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     disp = [per[k] for k in sorted(per)]
-    idx = [i for i, d in enumerate(disp) if d["name"].startswith("gemm_bf16_kernel")]
+    idx = [i for i, d in enumerate(disp) if d["name"].startswith("gemm_bf16")]
     per_sweep = sum(LAUNCHES[c] for c in SWEEP_GEMMS)
     idx = idx[-per_sweep * steps:]
     acc = {}

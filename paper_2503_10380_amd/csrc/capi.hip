@@ -267,9 +267,9 @@ Path path_for(cpppl_ctx* c, DType dt) {
 // c->launch_chunks launches along its batch, else along N in whole tiles.
 // Measured at o=32, v=256, X=768, R=1024: four launches per product raise the
 // sweep rate by 4 %, because the inverse then waits less at its join.
-void run_gemm(cpppl_ctx* c, const Path& P, const Gemm& g) {
+void run_gemm(cpppl_ctx* c, const Path& P, const Gemm& g, int max_chunks = 4) {
   hipStream_t s = c->stream;
-  const int k = c->launch_chunks;
+  const int k = std::min(c->launch_chunks, max_chunks);
   if (P.dt == DType::F64) {
     gemm_f64(g, s);
     return;
@@ -332,6 +332,13 @@ void compute_tau(cpppl_ctx* c, const Path& P) {
   run_gemm(c, P, g);
 }
 
+// Launches per Y and Z product while a side inverse is pending.  Both go to
+// the B-resident kernel, whose work-groups load a v x 256 block of B each, so
+// fewer, larger launches pay: measured at o = 32, v = 256, X = 768, R = 1024
+// alternating on one box, 391 sweeps/s with Y whole and Z in two launches,
+// 390 with Z whole, 385 with Z in four (Y in four: 6 % slower than whole).
+constexpr int Y_LAUNCHES = 1, Z_LAUNCHES = 2;
+
 // Y[r][X][q] = sum_p F[r][p] B^X_pq for F = factor `mode` (2 alpha with B,
 // 3 beta with the b-side operand: Dbar with singles, eq. dfB)
 void compute_Y(cpppl_ctx* c, const Path& P, int mode, size_t out) {
@@ -344,7 +351,7 @@ void compute_Y(cpppl_ctx* c, const Path& P, int mode, size_t out) {
   g.B = bside ? P.BnT_b : P.BnT; g.sbn = v; g.sbk = 1;
   g.b_fp8 = P.fp8; g.bscale = bside ? P.sBx_b : P.sBx; g.bscale_mode = 1;  // n = (X, q)
   g.C = c->at(out); g.scm = X * v; g.ctype = P.dt;
-  run_gemm(c, P, g);
+  run_gemm(c, P, g, Y_LAUNCHES);
 }
 
 // Z for mode a (contract d with tau[r][c][d]) or b (contract c).
@@ -357,7 +364,7 @@ void compute_Z(cpppl_ctx* c, const Path& P, int mode) {
   g.B = c->at(c->plan.tau); g.sbb = v * v;
   if (mode == 2) { g.sbn = v; g.sbk = 1; } else { g.sbk = v; g.sbn = 1; }
   g.C = c->at(c->plan.Z); g.scm = v; g.scb = X * v; g.ctype = P.dt;
-  run_gemm(c, P, g);
+  run_gemm(c, P, g, Z_LAUNCHES);
 }
 
 // M^T[r][p] = sum_{X,q} Z[r][X][q] B^X_pq  -> MT (FP64); mode 3 (beta)

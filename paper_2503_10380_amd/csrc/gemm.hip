@@ -707,6 +707,194 @@ void gemm_bf16_kernel(const KArgs a) {
   }
 }
 
+// ------------------------------------------------- short K, B in registers ----
+// C = alpha A B^T for a k-contiguous BF16 A (M x K) and a BF16 B (N x K, k or n
+// contiguous), with a short K (128 or 256) and a BF16 result, batched, unsplit: the shape of
+// Y = F^T B (one batch; K is a virtual dimension, N = X v runs to 10^5 and the
+// M x N result is four times the size of B) and of Z = Y tau per r (R batches
+// of X x v results from v x v operands).
+//
+// A work-group of eight waves owns 256 columns of one batch of C and a range of
+// its rows.
+// Each wave loads the fragments of its 32 columns of B over the whole of K once
+// (2 x K/32 fragments, 64 registers at K = 256; straight from memory when B is
+// k-contiguous, else through LDS in 32-deep slabs with transposing reads) and
+// keeps them for the work-group's life; blocks of 16 rows of A stream through LDS (two buffers,
+// the next block loaded into registers while the matrix cores work on the
+// current one), and each block's 16 x 256 results are staged in LDS and
+// written as whole 512-byte rows (stored straight from the accumulators, 32
+// bytes per row per instruction, they took twice as long as the products).
+// B is thus read from HBM once, with no LDS traffic, and the pipeline runs over
+// the rows instead of restarting every K = 256.
+// (Blocks of 32 rows need more than the 128 registers of four waves per SIMD.)
+// N must be a multiple of 256 and C 16-byte aligned with row and batch strides
+// that are multiples of 8.
+// Per fragment the arithmetic (one v_mfma_f32_16x16x32_bf16 per 32 k, in
+// increasing k) is that of gemm_bf16_kernel, so both give the same bits.
+// Offsets are 32-bit byte offsets from the operand bases (the launcher checks
+// that they fit), which lets every load and store address a uniform base.
+constexpr int RES_WAVES = 8, RES_COLS = 32 * RES_WAVES, RES_ROWS = 16;
+
+struct ResArgs {
+  const char* A;
+  int64_t sam, sab;  // elements
+  const char* B;
+  int64_t sbn, sbk, sbb;  // one of sbn, sbk is 1
+  char* C;
+  int64_t scm, scb;
+  int64_t M, N;
+  float alpha;
+  int nblk;         // column blocks per batch
+  int msplit;       // row ranges per column block
+  int64_t mchunk;   // row blocks per row range
+};
+
+template <int KS, bool BKC>
+__global__ __launch_bounds__(64 * RES_WAVES, 4) void gemm_bf16_bres_kernel(const ResArgs r) {
+  constexpr int K = 32 * KS, CPR = K / 8, NT = 64 * RES_WAVES;
+  constexpr int TC = RES_ROWS * CPR;          // 16-byte chunks of a row block
+  constexpr int LPT = (TC + NT - 1) / NT;     // per lane (the last lanes idle if TC < NT)
+  static_assert(TC % NT == 0 || TC < NT, "row block must divide over the lanes");
+  constexpr int ABUF = RES_ROWS * K;        // bf16 per LDS buffer
+  constexpr int CBUF = RES_ROWS * RES_COLS;  // bf16 per result staging buffer
+  // a B stored with n contiguous is brought in 32-deep slabs through LDS
+  using TB = BfTile<RES_COLS, false, 32, NT>;
+  constexpr int SMEM_RUN = 2 * (2 * ABUF + 2 * CBUF), SMEM_B = BKC ? 0 : 2 * TB::SIZE;
+  __shared__ __attribute__((aligned(16))) char smem[SMEM_RUN > SMEM_B ? SMEM_RUN : SMEM_B];
+  bf16_t* const As = (bf16_t*)smem;
+  bf16_t* const Cs = As + 2 * ABUF;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // each XCD takes a contiguous range of (batch, column block, row range)
+  // triples, so the row ranges of one column block share its B in that XCD's L2
+  const uint32_t G = gridDim.x;
+  const uint32_t vid = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+  const uint32_t bn = vid / (uint32_t)r.msplit;
+  const int64_t bt = bn / (uint32_t)r.nblk;
+  const int64_t n0 = (int64_t)(bn % (uint32_t)r.nblk) * RES_COLS;
+  const int64_t nrb = (r.M + RES_ROWS - 1) / RES_ROWS;
+  const int64_t rb0 = (int64_t)(vid % (uint32_t)r.msplit) * r.mchunk;
+  const int64_t rb1 = min(nrb, rb0 + r.mchunk);
+  if (rb0 >= rb1) return;  // the whole work-group
+  const char* const Ab = r.A + 2 * bt * r.sab;  // this batch's operands (uniform)
+  const char* const Bb = r.B + 2 * bt * r.sbb;
+  char* const Cb = r.C + 2 * bt * r.scb;
+
+  // B fragments of this wave: lane l holds column n0 + 32 w + 16 ct + l % 16,
+  // k = 32 ks + 8 (l / 16) .. + 7
+  bf16x8_t bfr[2][KS];
+  if constexpr (BKC) {
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const uint32_t n = (uint32_t)(n0 + w * 32 + ct * 16 + (lane & 15));
+      const uint32_t off = 2u * (n * (uint32_t)r.sbn + 8u * (lane >> 4));
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) bfr[ct][ks] = *(const bf16x8_t*)(Bb + (off + 64u * ks));
+    }
+  } else {
+    // slab ks: rows k = 32 ks .. + 31 of B (n contiguous, row stride sbk) as
+    // [k][n] in LDS, then each wave's fragments by transposing reads
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      uint4 rb[TB::C];
+      TB::template load<true>(rb, (const bf16_t*)Bb, 1, r.sbk, n0, n0 + RES_COLS, 32 * ks, K, true, tid);
+      if (ks > 0) __syncthreads();  // the previous slab's fragment reads are done
+      TB::store(rb, (bf16_t*)smem, tid);
+      __syncthreads();
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) bfr[ct][ks] = TB::frag((const bf16_t*)smem, w * 32 + ct * 16, 0, lane);
+    }
+    __syncthreads();  // the slab region is reused by the row blocks
+  }
+  // Wait for them here: a first use inside the row loop would leave a wait for
+  // every memory operation in flight (the next row block, the last block's
+  // stores) in each trip.
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) asm volatile("" ::"v"(__builtin_bit_cast(u32x4, bfr[ct][ks])));
+
+  // A row blocks: [16 rows][K] with the 16-byte chunk index XOR-ed with the
+  // row, so that the 16 rows of a fragment read (one chunk each) and the 16
+  // consecutive chunks of a row written by 16 lanes fall on distinct banks.
+  uint4 ra[LPT];
+  auto load_a = [&](int64_t rb) {
+#pragma unroll
+    for (int e = 0; e < LPT; ++e) {
+      const int c = tid + e * NT;
+      if (TC < NT && c >= TC) break;
+      const uint32_t g = (uint32_t)min(rb * RES_ROWS + c / CPR, r.M - 1);  // rows past M clamped
+      ra[e] = load16((const bf16_t*)(Ab + 2u * (g * (uint32_t)r.sam + (uint32_t)(c % CPR) * 8u)));
+    }
+  };
+  auto store_a = [&](bf16_t* S) {
+#pragma unroll
+    for (int e = 0; e < LPT; ++e) {
+      const int c = tid + e * NT;
+      if (TC < NT && c >= TC) break;
+      const int row = c / CPR, ch = c % CPR;
+      *(uint4*)&S[row * K + ((ch ^ row) << 3)] = ra[e];
+    }
+  };
+
+  // The loop body runs the same memory operations on every trip (block
+  // indices clamped to the last block, rows to the last row), so that the
+  // compiler waits only for the block about to be written to LDS and leaves
+  // the last block's stores in flight.
+  load_a(rb0);
+  store_a(As);
+  load_a(min(rb0 + 1, rb1 - 1));
+  __syncthreads();
+  const int lr = lane & 15;
+  auto trip = [&](int64_t rb) {
+    const int cur = (int)((rb - rb0) & 1);
+    const bf16_t* S = As + cur * ABUF;
+    f4_t acc[2] = {f4_t{0.f, 0.f, 0.f, 0.f}, f4_t{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const bf16x8_t af = *(const bf16x8_t*)&S[lr * K + (((ks * 4 + (lane >> 4)) ^ lr) << 3)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j][ks], af, acc[j], 0, 0, 0);
+    }
+    // Results to LDS (staging buffer cur, [16 rows][256 columns] with the
+    // 16-byte chunk index XOR-ed with the row): lane l holds row l % 16,
+    // columns 32 w + 16 j + 4 (l / 16) .. + 3.
+    bf16_t* Cc = Cs + cur * CBUF;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = w * 32 + j * 16 + 4 * (lane >> 4);
+      const uint32_t w0 = pack_bf16x2(r.alpha * acc[j][0], r.alpha * acc[j][1]);
+      const uint32_t w1 = pack_bf16x2(r.alpha * acc[j][2], r.alpha * acc[j][3]);
+      *(uint2*)&Cc[lr * RES_COLS + (((col >> 3) ^ lr) << 3) + (col & 7)] = make_uint2(w0, w1);
+    }
+    // A buffer cur ^ 1 was last read before the previous barrier; on the last
+    // trip it receives a copy of the last block that nobody reads
+    store_a(As + (cur ^ 1) * ABUF);
+    load_a(min(rb + 2, rb1 - 1));
+    __syncthreads();
+    // Whole rows to memory: 32 lanes per 512-byte row, 16 bytes each.  (Staging
+    // buffer cur is written again two trips on, after the next barrier.)  A row
+    // past M was computed from the clamped last row of A, so it equals row
+    // M - 1 and is stored there (the same bits twice).
+    {
+      const int row = tid >> 5, ch = tid & 31;
+      const uint32_t gm = (uint32_t)min(rb * RES_ROWS + row, r.M - 1);
+      typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+      const u32x4 v = *(const u32x4*)&Cc[row * RES_COLS + ((ch ^ row) << 3)];
+      __builtin_nontemporal_store(
+          v, (u32x4*)(Cb + 2u * (gm * (uint32_t)r.scm + (uint32_t)n0 + 8u * ch)));
+    }
+  };
+  // The first trip is peeled: in the loop the memory operations in flight at
+  // the top are then always the next block's loads followed by the last
+  // block's stores, and the wait before the next block's LDS write leaves the
+  // stores in flight.
+  trip(rb0);
+  for (int64_t rb = rb0 + 1; rb < rb1; ++rb) trip(rb);
+}
+
 // Sums the split-K partials in split order and applies alpha / beta.
 template <typename PT, typename OutT>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const PT* __restrict__ part, int splits,
@@ -862,6 +1050,34 @@ static void launch_bf16_layout(const KArgs& a, bool ak, bool bk, DType ct, dim3 
   else launch_bf16<BK, false, false, false, 2, FAST>(a, ct, grid, s);
 }
 
+// About three rounds of work-groups at two per CU, each over at least eight
+// row blocks.
+static void launch_bres(const Gemm& g, hipStream_t s) {
+  ResArgs r;
+  r.A = (const char*)g.A; r.sam = g.sam; r.sab = g.sab;
+  r.B = (const char*)g.B; r.sbn = g.sbn; r.sbk = g.sbk; r.sbb = g.sbb;
+  r.C = (char*)g.C; r.scm = g.scm; r.scb = g.scb;
+  r.M = g.M; r.N = g.N;
+  r.alpha = (float)g.alpha;
+  const int64_t nblk = (g.N + RES_COLS - 1) / RES_COLS;
+  const int64_t cols = nblk * g.batch;  // column blocks over all batches
+  const int64_t nrb = (g.M + RES_ROWS - 1) / RES_ROWS;
+  int64_t ms = std::max<int64_t>(1, std::min<int64_t>((1536 + cols - 1) / cols, nrb / 8));
+  r.mchunk = (nrb + ms - 1) / ms;
+  ms = (nrb + r.mchunk - 1) / r.mchunk;
+  r.msplit = (int)ms;
+  r.nblk = (int)nblk;
+  const int64_t blocks = cols * ms;
+  if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_bf16: grid too large");
+  const dim3 grid((unsigned)blocks), block(64 * RES_WAVES);
+  const bool bk = g.sbk == 1;
+  if (g.K == 256 && bk) hipLaunchKernelGGL((gemm_bf16_bres_kernel<8, true>), grid, block, 0, s, r);
+  else if (g.K == 256) hipLaunchKernelGGL((gemm_bf16_bres_kernel<8, false>), grid, block, 0, s, r);
+  else if (bk) hipLaunchKernelGGL((gemm_bf16_bres_kernel<4, true>), grid, block, 0, s, r);
+  else hipLaunchKernelGGL((gemm_bf16_bres_kernel<4, false>), grid, block, 0, s, r);
+  CPPPL_LAUNCH_CHECK("gemm_bf16 (B in registers)");
+}
+
 void gemm_bf16(const Gemm& g, hipStream_t s) {
   check_operand_strides(g);
   if (g.beta != 0.0 && g.splits <= 1) throw std::invalid_argument("gemm_bf16: beta must be 0");
@@ -907,6 +1123,18 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
   // G's longer K (X = 1152) 10 % slower.  Without the early load the second
   // tile's loads queue behind the first tile's stores, and chained products
   // took twice as long.
+  // Short-K products of a k-contiguous A over many columns with a BF16
+  // result (Y = F^T B, Z = Y tau per r): B kept in registers, A streamed (see
+  // gemm_bf16_bres_kernel).
+  if (!g.b_fp8 && ak && a.splits <= 1 && g.ctype == DType::BF16 &&
+      (g.K == 128 || g.K == 256) && a.vec_ok && g.N % RES_COLS == 0 &&
+      g.N * g.batch >= 16 * RES_COLS && g.M >= 8 * RES_ROWS && ((uintptr_t)g.C & 15) == 0 &&
+      g.scm % 8 == 0 && g.scb % 8 == 0 && g.sam >= g.K && g.N <= g.scm &&
+      (bk ? g.sbn >= g.K : g.sbk >= g.N) && g.M * g.sam < (1LL << 31) &&
+      (bk ? g.N * g.sbn : g.K * g.sbk) < (1LL << 31) && g.M * g.scm < (1LL << 31)) {
+    launch_bres(g, s);
+    return;
+  }
   const bool four = (ak && bk) || (fast && !ak && !bk);
   const bool chain = fast && !g.b_fp8 && BM == 128 && bk_slice == BBK_SHORT && four &&
                      (g.ctype != DType::F64 || a.splits > 1) && blocks >= BF16_CHAIN_MIN_TILES &&

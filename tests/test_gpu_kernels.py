@@ -174,12 +174,60 @@ def test_gemm_bf16_chained(env, layout, out, case):
     assert err <= (5e-5 if out == "f32" else 8e-3), err
 
 
+RESIDENT = [
+    # (M, N, K, batch, pad): two k-contiguous operands, K of 128 or 256, N a
+    # multiple of 256, at least 16 column blocks over the batches, at least 128
+    # rows, a BF16 result
+    (1024, 4096, 256, 1, 0),   # row blocks and row ranges divide evenly
+    (1000, 8192, 256, 1, 8),   # ragged last row block, padded operand rows
+    (300, 4608, 128, 1, 0),    # K = 128: half the lanes load each row block
+    (128, 4096, 256, 1, 0),    # eight row blocks, one row range
+    (200, 256, 256, 20, 8),    # batched (the shape of Z = Y tau per r), ragged rows
+    (768, 512, 128, 9, 0),     # batched, two column blocks per batch, K = 128
+]
+
+
+@pytest.mark.parametrize("bk", [True, False])
+@pytest.mark.parametrize("case", RESIDENT)
+def test_gemm_bf16_b_resident(env, case, bk):
+    """Short-K products of a k-contiguous A over many columns with a BF16
+    result (the shapes of Y = F^T B and of Z = Y tau per r, B k- or
+    n-contiguous) keep B in registers and stream A.  Checked against numpy, and
+    bit for bit against the tiled kernel: the same product written with a C row
+    stride that is not a multiple of 8 goes there (the padding columns must
+    stay untouched)."""
+    L, torch = env
+    M, N, K, batch, pad = case
+    _say(f"gemm bf16 B resident bk={bk} case={case}")
+    rng = np.random.default_rng(zlib.crc32(repr(("resident", M, N, K, batch, pad, bk)).encode()))
+    a, ta, sam, sak, sab = _operand(torch, rng, batch, M, K, 1, "bf16", pad=pad)
+    b, tb, sbk, sbn, sbb = _operand(torch, rng, batch, K, N, 0 if bk else 1, "bf16", pad=pad)
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for scm in (N, N + 4):
+        tc = torch.full((batch * M * scm,), 7.0, dtype=torch.bfloat16, device="cuda")
+        st = L.cpppl_test_gemm(1, M, N, K, batch, ta.data_ptr(), sam, sak, sab, tb.data_ptr(), sbk,
+                               sbn, sbb, tc.data_ptr(), scm, M * scm, 2, 0.5, 0.0, 1, None, stream)
+        assert st == 0
+        full = tc.view(batch, M, scm)
+        if scm > N:
+            assert torch.all(full[:, :, N:].float() == 7.0)
+        out[scm] = full[:, :, :N].contiguous()
+    torch.cuda.synchronize()
+    assert torch.equal(out[N].view(torch.int16), out[N + 4].view(torch.int16))
+    want = 0.5 * np.matmul(a, b)
+    got = out[N].to(torch.float64).cpu().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err <= 8e-3, err
+
+
 @pytest.mark.parametrize("which", ["Y", "Z"])
 def test_gemm_bf16_chained_bitwise(env, which):
-    """At o = 32, v = 256, X = 768, R = 1024 the ALS sweep cuts Y = F^T B and
-    Z = Y tau (per r) into four launches of 3072 tiles, which run two tiles per
-    work-group; a whole product (12288 tiles) runs one per work-group.  Each
-    tile's arithmetic is the same, so the two must agree bit for bit."""
+    """At o = 32, v = 256, X = 768, R = 1024 the ALS sweep may cut Y = F^T B and
+    Z = Y tau (per r) into launches along N or the batch, which changes each
+    launch's grid (tiles per work-group, row ranges per column block) but not
+    the arithmetic of an element, so a whole product and one cut into four must
+    agree bit for bit."""
     L, torch = env
     v, X, R = 256, 768, 1024
     _say(f"gemm bf16 chained vs whole, {which} at v={v} X={X} R={R}")
