@@ -317,6 +317,15 @@ int splits_for(cpppl_ctx* c, const Path& P, int64_t M, int64_t N, int64_t K, int
 }
 
 // ------------------------------------------------------------------ chain steps
+// Launches per Y and Z product while a side inverse is pending.  Both go to
+// the B-resident kernel, whose work-groups load a v x 256 block of B each, so
+// fewer, larger launches pay: measured at o = 32, v = 256, X = 768, R = 1024
+// alternating on one box, 391 sweeps/s with Y whole and Z in two launches,
+// 390 with Z whole, 385 with Z in four (Y in four: 6 % slower than whole).
+constexpr int Y_LAUNCHES = 1, Z_LAUNCHES = 2;
+// tau and G (tiled kernel) keep four.
+constexpr int TAU_LAUNCHES = 4, G_LAUNCHES = 4;
+
 // tau[r][cd] = sum_ij Kt[r][ij] t[ij][cd], Kt = KR(gamma, rho)   (path dtype)
 void compute_tau(cpppl_ctx* c, const Path& P) {
   Span sp(c, CPPPL_T_KR_T2);
@@ -329,15 +338,9 @@ void compute_tau(cpppl_ctx* c, const Path& P) {
   g.A = c->at(c->plan.Kt); g.sam = o * o; g.sak = 1;
   g.B = P.T2T; g.sbn = o * o; g.sbk = 1; g.b_fp8 = P.fp8;
   g.C = c->at(c->plan.tau); g.scm = v * v; g.ctype = P.dt;
-  run_gemm(c, P, g);
+  run_gemm(c, P, g, TAU_LAUNCHES);
 }
 
-// Launches per Y and Z product while a side inverse is pending.  Both go to
-// the B-resident kernel, whose work-groups load a v x 256 block of B each, so
-// fewer, larger launches pay: measured at o = 32, v = 256, X = 768, R = 1024
-// alternating on one box, 391 sweeps/s with Y whole and Z in two launches,
-// 390 with Z whole, 385 with Z in four (Y in four: 6 % slower than whole).
-constexpr int Y_LAUNCHES = 1, Z_LAUNCHES = 2;
 
 // Y[r][X][q] = sum_p F[r][p] B^X_pq for F = factor `mode` (2 alpha with B,
 // 3 beta with the b-side operand: Dbar with singles, eq. dfB)
@@ -393,7 +396,7 @@ void compute_G(cpppl_ctx* c, const Path& P) {
   g.A = c->at(c->plan.Ya); g.sam = 1; g.sak = v; g.sab = X * v;
   g.B = c->at(c->plan.Yb); g.sbk = v; g.sbn = 1; g.sbb = X * v;
   g.C = c->at(c->plan.Z); g.scm = v; g.scb = v * v; g.ctype = P.dt;
-  run_gemm(c, P, g);
+  run_gemm(c, P, g, G_LAUNCHES);
 }
 
 // H^T[r][ij] = sum_cd G[r][cd] t[ij][cd]  -> HT (FP64)
