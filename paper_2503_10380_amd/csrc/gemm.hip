@@ -709,13 +709,13 @@ void gemm_bf16_kernel(const KArgs a) {
 
 // ------------------------------------------------- short K, B in registers ----
 // C = alpha A B^T for a k-contiguous BF16 A (M x K) and a BF16 B (N x K, k or n
-// contiguous), with a short K (128 or 256) and a BF16 result, batched, unsplit: the shape of
+// contiguous), with a short K (128, 256 or 384) and a BF16 result, batched, unsplit: the shape of
 // Y = F^T B (one batch; K is a virtual dimension, N = X v runs to 10^5 and the
 // M x N result is four times the size of B) and of Z = Y tau per r (R batches
 // of X x v results from v x v operands).
 //
 // A work-group of eight waves owns 256 columns of one batch of C and a range of
-// its rows.
+// its rows (four waves and 128 columns at K = 384).
 // Each wave loads the fragments of its 32 columns of B over the whole of K once
 // (2 x K/32 fragments, 64 registers at K = 256; straight from memory when B is
 // k-contiguous, else through LDS in 32-deep slabs with transposing reads) and
@@ -727,13 +727,17 @@ void gemm_bf16_kernel(const KArgs a) {
 // B is thus read from HBM once, with no LDS traffic, and the pipeline runs over
 // the rows instead of restarting every K = 256.
 // (Blocks of 32 rows need more than the 128 registers of four waves per SIMD.)
-// N must be a multiple of 256 and C 16-byte aligned with row and batch strides
-// that are multiples of 8.
+// N must be a multiple of the work-group's columns and C 16-byte aligned with
+// row and batch strides that are multiples of 8.
 // Per fragment the arithmetic (one v_mfma_f32_16x16x32_bf16 per 32 k, in
 // increasing k) is that of gemm_bf16_kernel, so both give the same bits.
 // Offsets are 32-bit byte offsets from the operand bases (the launcher checks
 // that they fit), which lets every load and store address a uniform base.
-constexpr int RES_WAVES = 8, RES_COLS = 32 * RES_WAVES, RES_ROWS = 16;
+constexpr int RES_ROWS = 16;
+// eight waves (256 columns, two work-groups per CU) for K = 128 and 256; four
+// waves (128 columns, three per CU) for K = 384, whose 96 registers of B
+// fragments leave room for three waves per SIMD only
+constexpr int res_waves(int64_t K) { return K == 384 ? 4 : 8; }
 
 struct ResArgs {
   const char* A;
@@ -749,9 +753,11 @@ struct ResArgs {
   int64_t mchunk;   // row blocks per row range
 };
 
-template <int KS, bool BKC>
-__global__ __launch_bounds__(64 * RES_WAVES, 4) void gemm_bf16_bres_kernel(const ResArgs r) {
-  constexpr int K = 32 * KS, CPR = K / 8, NT = 64 * RES_WAVES;
+template <int KS, bool BKC, int WAVES>
+__global__ __launch_bounds__(64 * WAVES, WAVES == 8 ? 4 : 3) void gemm_bf16_bres_kernel(const ResArgs r) {
+  constexpr int K = 32 * KS, CPR = K / 8, NT = 64 * WAVES;
+  constexpr int RES_COLS = 32 * WAVES, CPRC = RES_COLS / 8;  // columns, 16-byte chunks per result row
+  static_assert(RES_ROWS * CPRC == NT, "one result chunk per lane");
   constexpr int TC = RES_ROWS * CPR;          // 16-byte chunks of a row block
   constexpr int LPT = (TC + NT - 1) / NT;     // per lane (the last lanes idle if TC < NT)
   static_assert(TC % NT == 0 || TC < NT, "row block must divide over the lanes");
@@ -874,12 +880,12 @@ __global__ __launch_bounds__(64 * RES_WAVES, 4) void gemm_bf16_bres_kernel(const
     store_a(As + (cur ^ 1) * ABUF);
     load_a(min(rb + 2, rb1 - 1));
     __syncthreads();
-    // Whole rows to memory: 32 lanes per 512-byte row, 16 bytes each.  (Staging
+    // Whole rows to memory: 16 bytes per lane, CPRC lanes per row.  (Staging
     // buffer cur is written again two trips on, after the next barrier.)  A row
     // past M was computed from the clamped last row of A, so it equals row
     // M - 1 and is stored there (the same bits twice).
     {
-      const int row = tid >> 5, ch = tid & 31;
+      const int row = tid / CPRC, ch = tid % CPRC;
       const uint32_t gm = (uint32_t)min(rb * RES_ROWS + row, r.M - 1);
       typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
       const u32x4 v = *(const u32x4*)&Cc[row * RES_COLS + ((ch ^ row) << 3)];
@@ -1059,22 +1065,26 @@ static void launch_bres(const Gemm& g, hipStream_t s) {
   r.C = (char*)g.C; r.scm = g.scm; r.scb = g.scb;
   r.M = g.M; r.N = g.N;
   r.alpha = (float)g.alpha;
-  const int64_t nblk = (g.N + RES_COLS - 1) / RES_COLS;
+  const int waves = res_waves(g.K), res_cols = 32 * waves;
+  const int64_t nblk = (g.N + res_cols - 1) / res_cols;
   const int64_t cols = nblk * g.batch;  // column blocks over all batches
   const int64_t nrb = (g.M + RES_ROWS - 1) / RES_ROWS;
-  int64_t ms = std::max<int64_t>(1, std::min<int64_t>((1536 + cols - 1) / cols, nrb / 8));
+  const int64_t target = 3 * 256 * (waves == 8 ? 2 : 3);  // three rounds of work-groups
+  int64_t ms = std::max<int64_t>(1, std::min<int64_t>((target + cols - 1) / cols, nrb / 8));
   r.mchunk = (nrb + ms - 1) / ms;
   ms = (nrb + r.mchunk - 1) / r.mchunk;
   r.msplit = (int)ms;
   r.nblk = (int)nblk;
   const int64_t blocks = cols * ms;
   if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_bf16: grid too large");
-  const dim3 grid((unsigned)blocks), block(64 * RES_WAVES);
+  const dim3 grid((unsigned)blocks), block(64 * waves);
   const bool bk = g.sbk == 1;
-  if (g.K == 256 && bk) hipLaunchKernelGGL((gemm_bf16_bres_kernel<8, true>), grid, block, 0, s, r);
-  else if (g.K == 256) hipLaunchKernelGGL((gemm_bf16_bres_kernel<8, false>), grid, block, 0, s, r);
-  else if (bk) hipLaunchKernelGGL((gemm_bf16_bres_kernel<4, true>), grid, block, 0, s, r);
-  else hipLaunchKernelGGL((gemm_bf16_bres_kernel<4, false>), grid, block, 0, s, r);
+  if (g.K == 384 && bk) hipLaunchKernelGGL((gemm_bf16_bres_kernel<12, true, 4>), grid, block, 0, s, r);
+  else if (g.K == 384) hipLaunchKernelGGL((gemm_bf16_bres_kernel<12, false, 4>), grid, block, 0, s, r);
+  else if (g.K == 256 && bk) hipLaunchKernelGGL((gemm_bf16_bres_kernel<8, true, 8>), grid, block, 0, s, r);
+  else if (g.K == 256) hipLaunchKernelGGL((gemm_bf16_bres_kernel<8, false, 8>), grid, block, 0, s, r);
+  else if (bk) hipLaunchKernelGGL((gemm_bf16_bres_kernel<4, true, 8>), grid, block, 0, s, r);
+  else hipLaunchKernelGGL((gemm_bf16_bres_kernel<4, false, 8>), grid, block, 0, s, r);
   CPPPL_LAUNCH_CHECK("gemm_bf16 (B in registers)");
 }
 
@@ -1127,8 +1137,8 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
   // result (Y = F^T B, Z = Y tau per r): B kept in registers, A streamed (see
   // gemm_bf16_bres_kernel).
   if (!g.b_fp8 && ak && a.splits <= 1 && g.ctype == DType::BF16 &&
-      (g.K == 128 || g.K == 256) && a.vec_ok && g.N % RES_COLS == 0 &&
-      g.N * g.batch >= 16 * RES_COLS && g.M >= 8 * RES_ROWS && ((uintptr_t)g.C & 15) == 0 &&
+      (g.K == 128 || g.K == 256 || g.K == 384) && a.vec_ok && g.N % (32 * res_waves(g.K)) == 0 &&
+      g.N * g.batch >= 16 * 32 * res_waves(g.K) && g.M >= 8 * RES_ROWS && ((uintptr_t)g.C & 15) == 0 &&
       g.scm % 8 == 0 && g.scb % 8 == 0 && g.sam >= g.K && g.N <= g.scm &&
       (bk ? g.sbn >= g.K : g.sbk >= g.N) && g.M * g.sam < (1LL << 31) &&
       (bk ? g.N * g.sbn : g.K * g.sbk) < (1LL << 31) && g.M * g.scm < (1LL << 31)) {

@@ -175,15 +175,17 @@ def test_gemm_bf16_chained(env, layout, out, case):
 
 
 RESIDENT = [
-    # (M, N, K, batch, pad): two k-contiguous operands, K of 128 or 256, N a
-    # multiple of 256, at least 16 column blocks over the batches, at least 128
-    # rows, a BF16 result
+    # (M, N, K, batch, pad): K of 128, 256 or 384, N a multiple of the
+    # work-group's columns (256, or 128 at K = 384), at least 16 column blocks
+    # over the batches, at least 128 rows, a BF16 result
     (1024, 4096, 256, 1, 0),   # row blocks and row ranges divide evenly
     (1000, 8192, 256, 1, 8),   # ragged last row block, padded operand rows
     (300, 4608, 128, 1, 0),    # K = 128: half the lanes load each row block
     (128, 4096, 256, 1, 0),    # eight row blocks, one row range
     (200, 256, 256, 20, 8),    # batched (the shape of Z = Y tau per r), ragged rows
     (768, 512, 128, 9, 0),     # batched, two column blocks per batch, K = 128
+    (300, 2304, 384, 1, 8),    # K = 384: four-wave work-groups of 128 columns
+    (200, 384, 384, 8, 0),     # K = 384, batched (the shape of Z at v = 384)
 ]
 
 
