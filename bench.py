@@ -239,6 +239,31 @@ def dominant_class(rep, rooflines, tie=0.05):
     return min(tied, key=lambda k: rooflines[k]["frac"])
 
 
+def cpu_baseline_whole(cfg, inp, fs, sweeps=2):
+    """The FP64 oracle on the whole workload: R formed explicitly, then
+    `sweeps` textbook ALS sweeps from the seeded start, timed (about 25 s of CPU
+    work at o = 32, v = 256, X = 768, R = 1024 on 16 cores)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    t0 = time.perf_counter()
+    r = oracle.form_r(inp.t, inp.b_vv)
+    t_form = time.perf_counter() - t0
+    print(f"cpu baseline: R formed in {t_form:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    oracle.cp_als(r, fs, sweeps, norm_r2=float(np.sum(r * r)))
+    t_als = time.perf_counter() - t0
+    return {
+        "value": sweeps / t_als, "unit": "sweeps/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"{cfg.name} whole: R formed explicitly ({t_form:.1f} s), then {sweeps} textbook "
+                   f"FP64 ALS sweeps from the seeded start, timed"),
+        "r_formation_s": t_form, "sweeps": sweeps, "als_s": t_als,
+    }
+
+
 def cpu_baseline(cfg, inp, fs, occ=8):
     """The FP64 oracle on a bounded sample: R for the i, j < occ pairs, then one
     textbook ALS sweep on that sub-tensor.  MTTKRP work is linear in the number
@@ -278,9 +303,11 @@ def cpu_baseline(cfg, inp, fs, occ=8):
 
 
 def cpu_oracle_runs(args):
-    """The FP64 oracle run whole on the host cores (the CPU baseline of the
-    small workloads): C1 (R formed, 50 sweeps) and C2 (R formed, 30 sweeps),
-    from the seeded random start."""
+    """The FP64 oracle on the host cores, per workload: C1 (R formed, 50
+    sweeps) and C2 (R formed, 30 sweeps) whole; C3 with R formed whole and two
+    sweeps timed; C4 with R formed for the first amplitude step and two sweeps
+    timed; C5 extrapolated from the 6 x 6 occupied pairs (1/64 of the pairs:
+    R for those pairs and one sweep on that sub-tensor, MTTKRP time x64)."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
@@ -301,6 +328,29 @@ def cpu_oracle_runs(args):
         out["runs"][name] = {"r_formation_s": t_form, "sweeps": cfg.sweeps, "als_s": t_als,
                              "sweeps_per_s": cfg.sweeps / t_als, "fit": hist["fit"][-1]}
         print(f"cpu oracle {name}: {json.dumps(out['runs'][name])}", file=sys.stderr, flush=True)
+    for name in ("C3", "C4"):
+        cfg = synth.CONFIGS[name]
+        inp = synth.make_inputs(cfg)
+        fs = synth.init_factors(cfg)
+        t = inp.t if name == "C3" else inp.t + synth.perturbation(cfg, 0, inp.t)
+        print(f"cpu oracle {name}: forming R", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        r = oracle.form_r(t, inp.b_vv)
+        t_form = time.perf_counter() - t0
+        print(f"cpu oracle {name}: R formed in {t_form:.1f} s", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        _, _, hist = oracle.cp_als(r, fs, 2, norm_r2=float(np.sum(r * r)))
+        t_als = time.perf_counter() - t0
+        out["runs"][name] = {"r_formation_s": t_form, "sweeps": 2, "als_s": t_als,
+                             "sweeps_per_s": 2 / t_als, "fit": hist["fit"][-1]}
+        print(f"cpu oracle {name}: {json.dumps(out['runs'][name])}", file=sys.stderr, flush=True)
+        del r
+    cfg = synth.CONFIGS["C5"]
+    inp = synth.make_inputs(cfg)
+    fs = synth.init_factors(cfg)
+    print("cpu oracle C5: 6 x 6 pair sample", file=sys.stderr, flush=True)
+    out["runs"]["C5"] = dict(cpu_baseline(cfg, inp, fs, occ=6), extrapolated=True)
+    print(f"cpu oracle C5: {json.dumps(out['runs']['C5'])}", file=sys.stderr, flush=True)
     return out
 
 
@@ -886,7 +936,9 @@ def main():
             out["legs"][leg] = workload_leg(cp, torch, synth.CONFIGS[name], prec, args)
             torch.cuda.empty_cache()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, inp, fs)
+        # whole up to C3's size (R 0.5 GB, ~25 s), else the pair sample
+        whole = cfg.o ** 2 * cfg.v ** 2 * 8 <= (1 << 30)
+        out["cpu_baseline"] = cpu_baseline_whole(cfg, inp, fs) if whole else cpu_baseline(cfg, inp, fs)
     print(json.dumps(out))
 
 

@@ -129,3 +129,15 @@ def test_digest_mfma_groups_launches(tmp_path):
     for cls in bench.CLASSES:
         assert d[cls]["mfma_util"] == pytest.approx(busy[cls] / (16 * 10.0 / 8))
         assert d[cls]["launches"] == 2 * bench.SWEEP_GEMMS.count(cls) * bench.LAUNCHES[cls]
+
+
+def test_cpu_baseline_whole_small():
+    """The whole-workload CPU baseline forms R and times the requested sweeps
+    (run here on the small C1 workload)."""
+    cfg = synth.CONFIGS["C1"]
+    inp = synth.make_inputs(cfg)
+    fs = synth.init_factors(cfg)
+    out = bench.cpu_baseline_whole(cfg, inp, fs, sweeps=2)
+    assert out["kind"] == "oracle" and out["unit"] == "sweeps/s" and out["sweeps"] == 2
+    assert out["value"] > 0 and out["r_formation_s"] >= 0 and out["cores"] >= 1
+    assert "C1 whole" in out["sample"]
