@@ -744,6 +744,8 @@ struct ResArgs {
   int64_t sam, sab;  // elements
   const char* B;
   int64_t sbn, sbk, sbb;  // one of sbn, sbk is 1
+  const float* bscale;    // e4m3 B: per column (mode 1) or per k (mode 2)
+  int bscale_mode;
   char* C;
   int64_t scm, scb;
   int64_t M, N;
@@ -753,8 +755,9 @@ struct ResArgs {
   int64_t mchunk;   // row blocks per row range
 };
 
-template <int KS, bool BKC, int WAVES>
+template <int KS, bool BKC, int WAVES, bool B8 = false>
 __global__ __launch_bounds__(64 * WAVES, WAVES == 8 ? 4 : 3) void gemm_bf16_bres_kernel(const ResArgs r) {
+  static_assert(!B8 || BKC, "an e4m3 B operand must be k-contiguous");
   constexpr int K = 32 * KS, CPR = K / 8, NT = 64 * WAVES;
   constexpr int RES_COLS = 32 * WAVES, CPRC = RES_COLS / 8;  // columns, 16-byte chunks per result row
   static_assert(RES_ROWS * CPRC == NT, "one result chunk per lane");
@@ -789,7 +792,23 @@ __global__ __launch_bounds__(64 * WAVES, WAVES == 8 ? 4 : 3) void gemm_bf16_bres
   // B fragments of this wave: lane l holds column n0 + 32 w + 16 ct + l % 16,
   // k = 32 ks + 8 (l / 16) .. + 7
   bf16x8_t bfr[2][KS];
-  if constexpr (BKC) {
+  if constexpr (B8) {
+    // e4m3 codes (one byte each, batch 0 only), decoded exactly and scaled
+    // per column (mode 1) or per aligned group of 8 k (mode 2)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const uint32_t n = (uint32_t)(n0 + w * 32 + ct * 16 + (lane & 15));
+      const uint32_t off = n * (uint32_t)r.sbn + 8u * (lane >> 4);
+      const float sn = r.bscale_mode == 1 ? r.bscale[n] : 1.0f;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 q = *(const u32x2*)(r.B + (off + 32u * ks));
+        const float sc = r.bscale_mode == 2 ? r.bscale[32 * ks + 8 * (lane >> 4)] : sn;
+        bfr[ct][ks] = __builtin_bit_cast(bf16x8_t, e4m3x8_to_bf16(make_uint2(q[0], q[1]), sc));
+      }
+    }
+  } else if constexpr (BKC) {
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
       const uint32_t n = (uint32_t)(n0 + w * 32 + ct * 16 + (lane & 15));
@@ -1062,6 +1081,7 @@ static void launch_bres(const Gemm& g, hipStream_t s) {
   ResArgs r;
   r.A = (const char*)g.A; r.sam = g.sam; r.sab = g.sab;
   r.B = (const char*)g.B; r.sbn = g.sbn; r.sbk = g.sbk; r.sbb = g.sbb;
+  r.bscale = g.bscale; r.bscale_mode = g.b_fp8 ? g.bscale_mode : 0;
   r.C = (char*)g.C; r.scm = g.scm; r.scb = g.scb;
   r.M = g.M; r.N = g.N;
   r.alpha = (float)g.alpha;
@@ -1079,7 +1099,11 @@ static void launch_bres(const Gemm& g, hipStream_t s) {
   if (blocks > 0x7fffffffLL) throw std::invalid_argument("gemm_bf16: grid too large");
   const dim3 grid((unsigned)blocks), block(64 * waves);
   const bool bk = g.sbk == 1;
-  if (g.K == 384 && bk) hipLaunchKernelGGL((gemm_bf16_bres_kernel<12, true, 4>), grid, block, 0, s, r);
+  if (g.b_fp8) {
+    if (g.K == 384) hipLaunchKernelGGL((gemm_bf16_bres_kernel<12, true, 4, true>), grid, block, 0, s, r);
+    else if (g.K == 256) hipLaunchKernelGGL((gemm_bf16_bres_kernel<8, true, 8, true>), grid, block, 0, s, r);
+    else hipLaunchKernelGGL((gemm_bf16_bres_kernel<4, true, 8, true>), grid, block, 0, s, r);
+  } else if (g.K == 384 && bk) hipLaunchKernelGGL((gemm_bf16_bres_kernel<12, true, 4>), grid, block, 0, s, r);
   else if (g.K == 384) hipLaunchKernelGGL((gemm_bf16_bres_kernel<12, false, 4>), grid, block, 0, s, r);
   else if (g.K == 256 && bk) hipLaunchKernelGGL((gemm_bf16_bres_kernel<8, true, 8>), grid, block, 0, s, r);
   else if (g.K == 256) hipLaunchKernelGGL((gemm_bf16_bres_kernel<8, false, 8>), grid, block, 0, s, r);
@@ -1136,7 +1160,7 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
   // Short-K products of a k-contiguous A over many columns with a BF16
   // result (Y = F^T B, Z = Y tau per r): B kept in registers, A streamed (see
   // gemm_bf16_bres_kernel).
-  if (!g.b_fp8 && ak && a.splits <= 1 && g.ctype == DType::BF16 &&
+  if ((!g.b_fp8 || (bk && g.batch == 1)) && ak && a.splits <= 1 && g.ctype == DType::BF16 &&
       (g.K == 128 || g.K == 256 || g.K == 384) && a.vec_ok && g.N % (32 * res_waves(g.K)) == 0 &&
       g.N * g.batch >= 16 * 32 * res_waves(g.K) && g.M >= 8 * RES_ROWS && ((uintptr_t)g.C & 15) == 0 &&
       g.scm % 8 == 0 && g.scb % 8 == 0 && g.sam >= g.K && g.N <= g.scm &&

@@ -254,3 +254,61 @@ def test_fp8_sampled_columns_full_size(lib):
                           chain_lengths(cfg.o, cfg.v, cfg.nx, mode), f"C3 mode {mode}")
         _say(f"  mode {mode}: rel err {err:.2e}")
     ctx.close()
+
+
+RESIDENT_E4M3 = [
+    # (M, N, K, pad): shapes of Y = F^T B with an e4m3 B (batch 1, BF16 result),
+    # which go to the B-resident kernel
+    (300, 4096, 256, 8),     # ragged last row block
+    (256, 2304, 384, 0),     # K = 384: four-wave work-groups of 128 columns
+    (200, 4096, 128, 8),     # K = 128
+]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("case", RESIDENT_E4M3)
+def test_gemm_e4m3_b_resident(env, mode, case):
+    """e4m3 B in the B-resident kernel (fragments decoded once per work-group):
+    against the decoded product in numpy, and bit for bit against the tiled
+    kernel (the same product written with a C row stride that is not a multiple
+    of 8 goes there)."""
+    L, torch = env
+    M, N, K, pad = case
+    _say(f"gemm e4m3 B resident mode={mode} case={case}")
+    rng = np.random.default_rng(zlib.crc32(repr(("resident-e4m3", M, N, K, mode)).encode()))
+    a = rng.standard_normal((M, K))
+    a = torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    sam = K + pad
+    store_a = np.zeros((M, sam))
+    store_a[:, :K] = a
+    ta = torch.tensor(store_a.reshape(-1)).to(torch.bfloat16).cuda()
+    sbn = K + pad
+    codes = FINITE[rng.integers(0, len(FINITE), size=(N, sbn))]
+    tb = torch.tensor(codes.reshape(-1), dtype=torch.uint8).cuda()
+    if mode == 1:
+        scale = 2.0 ** rng.integers(-8, 4, size=N)
+        bmul = np.broadcast_to(scale[:, None], (N, K))
+    elif mode == 2:
+        scale = np.repeat(2.0 ** rng.integers(-8, 4, size=K // 8), 8)
+        bmul = np.broadcast_to(scale[None, :], (N, K))
+    else:
+        scale = np.ones(1)
+        bmul = np.ones((N, K))
+    tsc = torch.tensor(scale, dtype=torch.float32).cuda()
+    want = a @ (fp8.e4m3_decode(codes[:, :K]) * bmul).T
+    out = {}
+    for scm in (N, N + 4):
+        tc = torch.full((M * scm,), 7.0, dtype=torch.bfloat16, device="cuda")
+        st = L.cpppl_test_gemm_e4m3b(M, N, K, 1, ta.data_ptr(), sam, 1, 0, tb.data_ptr(), sbn, 0,
+                                     tsc.data_ptr(), mode, tc.data_ptr(), scm, 0, 2, 1, None,
+                                     _stream(torch))
+        assert st == 0
+        full = tc.view(M, scm)
+        if scm > N:
+            assert torch.all(full[:, N:].float() == 7.0)
+        out[scm] = full[:, :N].contiguous()
+    torch.cuda.synchronize()
+    assert torch.equal(out[N].view(torch.int16), out[N + 4].view(torch.int16))
+    got = out[N].to(torch.float64).cpu().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err <= 8e-3, err
