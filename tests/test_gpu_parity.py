@@ -504,3 +504,28 @@ def test_init_random_matches_oracle_generator(lib):
     _, _, hist = oracle.cp_als(r, want, 5, norm_r2=float(np.sum(r * r)))
     np.testing.assert_allclose(rep["fit_hist"], hist["fit"], rtol=0, atol=1e-9)
     ctx.close()
+
+
+def test_bf16_sampled_columns_full_size(lib):
+    """C3 sizes (o 32, v 256, X 768, R 1024) on the MP2-shaped inputs: sampled
+    columns r of the BF16 MTTKRP (Y and Z on the B-resident kernel, tau, M, G
+    and H on the tiled one) against the oracle's FP64 chain, within the derived
+    element-wise and norm-wise bounds (a column of the MTTKRP depends on column
+    r of the factors only)."""
+    cfg = synth.CONFIGS["C3"]
+    _say("bf16 sampled columns C3")
+    inp = synth.make_inputs(cfg)
+    fs = synth.init_factors(cfg)
+    ctx = lib.Context(cfg.o, cfg.v, cfg.nx, cfg.rank, "bf16")
+    ctx.load_t2(inp.t)
+    ctx.load_df(inp.b_vv)
+    ctx.set_factors(*fs)
+    cols = [0, 377, cfg.rank - 1]
+    sub = [f[:, cols] for f in fs]
+    for mode in range(4):
+        got = ctx.mttkrp(mode)[:, cols]
+        want = oracle.mttkrp_chain(inp.t, inp.b_vv, sub, mode)
+        err = assert_lowp(got, want, abs_chain(inp.t, inp.b_vv, sub, mode), N_ROUND_BF16,
+                          chain_lengths(cfg.o, cfg.v, cfg.nx, mode), f"C3 mode {mode}")
+        _say(f"  mode {mode}: rel err {err:.2e}")
+    ctx.close()
