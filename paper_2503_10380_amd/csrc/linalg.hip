@@ -16,9 +16,9 @@
 //
 // The 64 x 64 pivot inverse runs in registers, each wave holding a slab of
 // 16 rows in the f64 matrix-core result layout, as four 16-wide block sweeps.
-// The wave that owns a panel's rows inverts its 16 x 16 pivot block in place
-// (pivot by readlane, pivot column by a DPP row broadcast, pivot row by one
-// 64-bit bpermute, reciprocal refined by Newton steps) and publishes the
+// The wave that owns a panel's rows inverts its 16 x 16 pivot block in place,
+// two pivots per step (pivot block by readlane, pivot columns by DPP row
+// broadcasts, pivot rows by 64-bit bpermutes, reciprocal refined by Newton steps) and publishes the
 // inverse and its rows; the other waves form their column-panel products and
 // rank-16 updates on the matrix cores with operands taken from registers (the
 // matrix is symmetric, so the published pivot rows also give the pivot
@@ -149,56 +149,62 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 
 // In-wave Gauss-Jordan inverse (in place) of a 16 x 16 SPD block held in the
 // f64 matrix-core result layout: lane l holds column l % 16, rows 4 c + l / 16
-// in register c.  Pivot k sits in register k / 4 of lane 16 (k % 4) + k; the
-// pivot column at a lane's rows is in the same registers of lane 16 (l / 16) + k
-// (a broadcast inside each row of 16 lanes); the pivot row at a lane's column
-// is register k / 4 of lane 16 (k % 4) + l % 16.
+// in register c.  Element (i, j) is register i / 4 of lane 16 (i % 4) + j, so
+// the pivot rows at a lane's column come from lanes 16 (k % 4) + l % 16 and the
+// pivot columns at a lane's rows from lane 16 (l / 16) + k (a broadcast inside
+// each row of 16 lanes).
 //
-// Each pivot step is one rank-1 update g_ij -= c_i r_j with
-// r_j = (g_kj + [j = k]) / p and c_i = g_ik - [i = k]: for i, j != k this is the
-// elimination g_ij - g_ik g_kj / p, and it also turns the pivot row into
-// g_kj / p, the pivot column into -g_ik / p and the pivot into 1 / p, so no
-// entry needs a case of its own.
-__device__ __forceinline__ bool gj16_block(d4_t& g) {
+// The pivots are taken two at a time, K = {k, k + 1}, each step one rank-2
+// update g_ij -= C_i . R_j with R_j = D (g_Kj + e_K(j)), C_i = g_iK - e_K(i)
+// and D the inverse of the 2 x 2 pivot block [[a, b], [b, c]] (a c - b^2 > 0
+// for an SPD matrix).  For i, j outside K this is the block elimination
+// g_ij - g_iK D g_Kj; it also turns the pivot rows into D g_Kj, the pivot
+// columns into -g_iK D and the pivot block into D, which is what two single
+// pivot steps (pivot -> 1 / p, row -> g_kj / p, column -> -g_ik / p) leave, so
+// no entry needs a case of its own and the dependent chain is one 2 x 2
+// inverse per two pivots.
+template <int K>
+__device__ __forceinline__ bool gj16_pair_step(d4_t& g) {
+  constexpr int kr = K >> 2, kq = K & 3;  // rows K, K + 1: lane rows kq, kq + 1 of register kr
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, rq = lane >> 4;
-  bool ok = true;
+  const double a = readlane_f64(g[kr], 16 * kq + K);
+  const double b = readlane_f64(g[kr], 16 * kq + K + 1);
+  const double c = readlane_f64(g[kr], 16 * (kq + 1) + K + 1);
+  const double r0 = __shfl(g[kr], 16 * kq + col);        // g(K, col)
+  const double r1 = __shfl(g[kr], 16 * (kq + 1) + col);  // g(K + 1, col)
+  double c0[4], c1[4];                                   // g(row, K), g(row, K + 1)
 #pragma unroll
-  for (int k = 0; k < PW; ++k) {
-    const int kr = k >> 2, kq = k & 3;
-    double p = readlane_f64(g[kr], 16 * kq + k);
-    const bool bad = !(p > 0.0) || !isfinite(p);
-    ok = ok && !bad;
-    if (bad) p = 1.0;
-    const double rk = __shfl(g[kr], 16 * kq + col);
-    double ck[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      switch (k) {
-        case 0: ck[c] = row_bcast_f64<0>(g[c]); break;
-        case 1: ck[c] = row_bcast_f64<1>(g[c]); break;
-        case 2: ck[c] = row_bcast_f64<2>(g[c]); break;
-        case 3: ck[c] = row_bcast_f64<3>(g[c]); break;
-        case 4: ck[c] = row_bcast_f64<4>(g[c]); break;
-        case 5: ck[c] = row_bcast_f64<5>(g[c]); break;
-        case 6: ck[c] = row_bcast_f64<6>(g[c]); break;
-        case 7: ck[c] = row_bcast_f64<7>(g[c]); break;
-        case 8: ck[c] = row_bcast_f64<8>(g[c]); break;
-        case 9: ck[c] = row_bcast_f64<9>(g[c]); break;
-        case 10: ck[c] = row_bcast_f64<10>(g[c]); break;
-        case 11: ck[c] = row_bcast_f64<11>(g[c]); break;
-        case 12: ck[c] = row_bcast_f64<12>(g[c]); break;
-        case 13: ck[c] = row_bcast_f64<13>(g[c]); break;
-        case 14: ck[c] = row_bcast_f64<14>(g[c]); break;
-        default: ck[c] = row_bcast_f64<15>(g[c]); break;
-      }
-    }
-    const double inv = recip_nr(p);
-    const double r = (rk + (col == k ? 1.0 : 0.0)) * inv;
-    ck[kr] -= (rq == kq) ? 1.0 : 0.0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) g[c] = fma(-ck[c], r, g[c]);
+  for (int q = 0; q < 4; ++q) {
+    c0[q] = row_bcast_f64<K>(g[q]);
+    c1[q] = row_bcast_f64<K + 1>(g[q]);
   }
+  const double det = fma(-b, b, a * c);
+  // a pivot block that is not positive definite is flagged and inverted with
+  // 1 / det replaced by 1, so every entry stays finite
+  const bool bad = !(a > 0.0) || !(det > 0.0) || !isfinite(det);
+  double id = recip_nr(det);
+  if (bad) id = 1.0;
+  const double d00 = c * id, d01 = -b * id, d11 = a * id;
+  const double u0 = r0 + (col == K ? 1.0 : 0.0), u1 = r1 + (col == K + 1 ? 1.0 : 0.0);
+  const double R0 = fma(d00, u0, d01 * u1);
+  const double R1 = fma(d01, u0, d11 * u1);
+  c0[kr] -= (rq == kq) ? 1.0 : 0.0;
+  c1[kr] -= (rq == kq + 1) ? 1.0 : 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) g[q] = fma(-c0[q], R0, fma(-c1[q], R1, g[q]));
+  return !bad;
+}
+
+__device__ __forceinline__ bool gj16_block(d4_t& g) {
+  bool ok = gj16_pair_step<0>(g);
+  ok = gj16_pair_step<2>(g) && ok;
+  ok = gj16_pair_step<4>(g) && ok;
+  ok = gj16_pair_step<6>(g) && ok;
+  ok = gj16_pair_step<8>(g) && ok;
+  ok = gj16_pair_step<10>(g) && ok;
+  ok = gj16_pair_step<12>(g) && ok;
+  ok = gj16_pair_step<14>(g) && ok;
   return ok;
 }
 
