@@ -843,42 +843,55 @@ __global__ __launch_bounds__(64 * WAVES, WAVES == 8 ? 4 : 3) void gemm_bf16_bres
   // A row blocks: [16 rows][K] with the 16-byte chunk index XOR-ed with the
   // row, so that the 16 rows of a fragment read (one chunk each) and the 16
   // consecutive chunks of a row written by 16 lanes fall on distinct banks.
-  uint4 ra[LPT];
-  auto load_a = [&](int64_t rb) {
+  // They come through a ring of P register slots, P blocks ahead of the one in
+  // LDS.  Loads and stores retire in issue order, so waiting for a block's
+  // load also waits for every store issued before it: with P slots, P - 1
+  // trips' result stores stay in flight at that wait (one with two slots,
+  // which held Y's stores to about 3 TB/s).  K = 384 keeps two slots: its
+  // three loads per lane and slot would not fit in the registers left at
+  // three waves per SIMD.
+  constexpr int P = KS == 12 ? 2 : 4;
+  uint4 ra[P][LPT];
+  auto load_a = [&](uint4 (&slot)[LPT], int64_t rb) __attribute__((always_inline)) {
 #pragma unroll
     for (int e = 0; e < LPT; ++e) {
       const int c = tid + e * NT;
       if (TC < NT && c >= TC) break;
       const uint32_t g = (uint32_t)min(rb * RES_ROWS + c / CPR, r.M - 1);  // rows past M clamped
-      ra[e] = load16((const bf16_t*)(Ab + 2u * (g * (uint32_t)r.sam + (uint32_t)(c % CPR) * 8u)));
+      slot[e] = load16((const bf16_t*)(Ab + 2u * (g * (uint32_t)r.sam + (uint32_t)(c % CPR) * 8u)));
     }
   };
-  auto store_a = [&](bf16_t* S) {
+  auto store_a = [&](const uint4 (&slot)[LPT], bf16_t* S) __attribute__((always_inline)) {
 #pragma unroll
     for (int e = 0; e < LPT; ++e) {
       const int c = tid + e * NT;
       if (TC < NT && c >= TC) break;
       const int row = c / CPR, ch = c % CPR;
-      *(uint4*)&S[row * K + ((ch ^ row) << 3)] = ra[e];
+      *(uint4*)&S[row * K + ((ch ^ row) << 3)] = slot[e];
     }
   };
 
-  // The loop body runs the same memory operations on every trip (block
-  // indices clamped to the last block, rows to the last row), so that the
-  // compiler waits only for the block about to be written to LDS and leaves
-  // the last block's stores in flight.
-  load_a(rb0);
-  store_a(As);
-  load_a(min(rb0 + 1, rb1 - 1));
+  // Trip t computes row block min(rb0 + t, rb1 - 1): the trip count is padded
+  // to a multiple of P and the padding trips recompute and store the last
+  // block again (the same bits).  Every trip then runs the same memory
+  // operations, and the compiler waits only for the block about to be written
+  // to LDS.  Block t + 1 sits in slot (t + 1) % P and LDS buffer (t + 1) % 2.
+  const int64_t last = rb1 - 1;
+  load_a(ra[0], rb0);
+  store_a(ra[0], As);
+#pragma unroll
+  for (int q = 1; q <= P; ++q) load_a(ra[q % P], min(rb0 + q, last));
   __syncthreads();
   const int lr = lane & 15;
-  auto trip = [&](int64_t rb) {
-    const int cur = (int)((rb - rb0) & 1);
-    const bf16_t* S = As + cur * ABUF;
+  auto trip = [&](auto slot_c, int64_t t) __attribute__((always_inline)) {
+    constexpr int S = decltype(slot_c)::value;  // t % P
+    constexpr int cur = S & 1, nxt = (S + 1) % P;
+    const int64_t rb = min(rb0 + t, last);
+    const bf16_t* A_ = As + cur * ABUF;
     f4_t acc[2] = {f4_t{0.f, 0.f, 0.f, 0.f}, f4_t{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const bf16x8_t af = *(const bf16x8_t*)&S[lr * K + (((ks * 4 + (lane >> 4)) ^ lr) << 3)];
+      const bf16x8_t af = *(const bf16x8_t*)&A_[lr * K + (((ks * 4 + (lane >> 4)) ^ lr) << 3)];
 #pragma unroll
       for (int j = 0; j < 2; ++j)
         acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j][ks], af, acc[j], 0, 0, 0);
@@ -894,10 +907,9 @@ __global__ __launch_bounds__(64 * WAVES, WAVES == 8 ? 4 : 3) void gemm_bf16_bres
       const uint32_t w1 = pack_bf16x2(r.alpha * acc[j][2], r.alpha * acc[j][3]);
       *(uint2*)&Cc[lr * RES_COLS + (((col >> 3) ^ lr) << 3) + (col & 7)] = make_uint2(w0, w1);
     }
-    // A buffer cur ^ 1 was last read before the previous barrier; on the last
-    // trip it receives a copy of the last block that nobody reads
-    store_a(As + (cur ^ 1) * ABUF);
-    load_a(min(rb + 2, rb1 - 1));
+    // LDS buffer cur ^ 1 was last read before the previous barrier
+    store_a(ra[nxt], As + (cur ^ 1) * ABUF);
+    load_a(ra[nxt], min(rb0 + t + 1 + P, last));
     __syncthreads();
     // Whole rows to memory: 16 bytes per lane, CPRC lanes per row.  (Staging
     // buffer cur is written again two trips on, after the next barrier.)  A row
@@ -912,12 +924,19 @@ __global__ __launch_bounds__(64 * WAVES, WAVES == 8 ? 4 : 3) void gemm_bf16_bres
           v, (u32x4*)(Cb + 2u * (gm * (uint32_t)r.scm + (uint32_t)n0 + 8u * ch)));
     }
   };
-  // The first trip is peeled: in the loop the memory operations in flight at
-  // the top are then always the next block's loads followed by the last
-  // block's stores, and the wait before the next block's LDS write leaves the
-  // stores in flight.
-  trip(rb0);
-  for (int64_t rb = rb0 + 1; rb < rb1; ++rb) trip(rb);
+  auto group = [&](int64_t t0) __attribute__((always_inline)) {
+    trip(std::integral_constant<int, 0>{}, t0);
+    trip(std::integral_constant<int, 1>{}, t0 + 1);
+    if constexpr (P == 4) {
+      trip(std::integral_constant<int, 2>{}, t0 + 2);
+      trip(std::integral_constant<int, 3>{}, t0 + 3);
+    }
+  };
+  // The first group is peeled: in the loop the memory operations in flight at
+  // the top are then always the next blocks' loads and the last trips' stores.
+  const int64_t ntrip = (rb1 - rb0 + P - 1) / P * P;
+  group(0);
+  for (int64_t t0 = P; t0 < ntrip; t0 += P) group(t0);
 }
 
 // Sums the split-K partials in split order and applies alpha / beta.
