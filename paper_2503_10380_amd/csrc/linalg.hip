@@ -18,12 +18,13 @@
 // 16 rows in the f64 matrix-core result layout, as four 16-wide block sweeps.
 // The wave that owns a panel's rows inverts its 16 x 16 pivot block in place,
 // two pivots per step (pivot block by readlane, pivot columns by DPP row
-// broadcasts, pivot rows by 64-bit bpermutes, reciprocal refined by Newton steps) and publishes the
-// inverse and its rows; the other waves form their column-panel products and
-// rank-16 updates on the matrix cores with operands taken from registers (the
-// matrix is symmetric, so the published pivot rows also give the pivot
-// columns).  The owner of the next panel updates its rows first and starts the
-// next pivot inverse while the others finish, so a panel needs one barrier.
+// broadcasts, pivot rows by 64-bit bpermutes, reciprocal refined by Newton
+// steps) and publishes the inverse and its rows; the other waves form their
+// column-panel products and rank-16 updates on the matrix cores with operands
+// taken from registers (the matrix is symmetric, so the published pivot rows
+// also give the pivot columns).  The owner of the next panel updates its rows
+// first and starts the next pivot inverse while the others finish, so a panel
+// needs one barrier.
 #include "linalg.h"
 
 #include <utility>
@@ -220,7 +221,7 @@ __device__ __forceinline__ int sl_col(int j) { return 16 * j + (threadIdx.x & 15
 // P <- P^{-1} for the NB x NB SPD tile held as a slab.  The tile is first
 // scaled to unit diagonal, S P S with S = diag(P)^{-1/2}, so that every pivot
 // met afterwards (a Schur complement of a unit-diagonal SPD matrix) is at most
-// 1, where the uniform pivot step of gj16_block loses no precision; the result
+// 1, where the uniform pivot steps of gj16_block lose no precision; the result
 // is scaled back, P^{-1} = S (S P S)^{-1} S.  A diagonal entry that is <= 0 or
 // not finite counts as a bad pivot and is replaced by 1.  Then four 16-wide
 // block sweeps (they leave -P^{-1}, negated at the end).  Panel p: wave p
