@@ -709,21 +709,22 @@ void gemm_bf16_kernel(const KArgs a) {
 
 // ------------------------------------------------- short K, B in registers ----
 // C = alpha A B^T for a k-contiguous BF16 A (M x K) and a BF16 B (N x K, k or n
-// contiguous), with a short K (128, 256 or 384) and a BF16 result, batched, unsplit: the shape of
-// Y = F^T B (one batch; K is a virtual dimension, N = X v runs to 10^5 and the
-// M x N result is four times the size of B) and of Z = Y tau per r (R batches
-// of X x v results from v x v operands).
+// contiguous), with a short K (128, 256 or 384) and a BF16 result, batched,
+// unsplit: the shape of Y = F^T B (one batch; K is a virtual dimension, N = X v
+// runs to 10^5 and the M x N result is four times the size of B) and of
+// Z = Y tau per r (R batches of X x v results from v x v operands).
 //
 // A work-group of eight waves owns 256 columns of one batch of C and a range of
 // its rows (four waves and 128 columns at K = 384).
 // Each wave loads the fragments of its 32 columns of B over the whole of K once
 // (2 x K/32 fragments, 64 registers at K = 256; straight from memory when B is
 // k-contiguous, else through LDS in 32-deep slabs with transposing reads) and
-// keeps them for the work-group's life; blocks of 16 rows of A stream through LDS (two buffers,
-// the next block loaded into registers while the matrix cores work on the
-// current one), and each block's 16 x 256 results are staged in LDS and
-// written as whole 512-byte rows (stored straight from the accumulators, 32
-// bytes per row per instruction, they took twice as long as the products).
+// keeps them for the work-group's life; blocks of 16 rows of A stream through
+// LDS (two buffers, fed by a ring of register slots up to four blocks ahead
+// while the matrix cores work on the current one), and each block's 16 x 256
+// results are staged in LDS and written as whole 512-byte rows (stored straight
+// from the accumulators, 32 bytes per row per instruction, they took twice as
+// long as the products).
 // B is thus read from HBM once, with no LDS traffic, and the pipeline runs over
 // the rows instead of restarting every K = 256.
 // (Blocks of 32 rows need more than the 128 registers of four waves per SIMD.)
