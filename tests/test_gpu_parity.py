@@ -529,3 +529,27 @@ def test_bf16_sampled_columns_full_size(lib):
                           chain_lengths(cfg.o, cfg.v, cfg.nx, mode), f"C3 mode {mode}")
         _say(f"  mode {mode}: rel err {err:.2e}")
     ctx.close()
+
+
+def test_bf16_sampled_columns_full_size_c5(lib):
+    """C5 sizes (o 48, v 384, X 1152, R 2048) on the MP2-shaped inputs: sampled
+    columns r of the BF16 MTTKRP for one occupied and one virtual mode (Y and Z
+    on the B-resident kernel's four-wave, 128-column work-groups at K = v = 384)
+    against the oracle's FP64 chain, within the derived bounds."""
+    cfg = synth.CONFIGS["C5"]
+    _say("bf16 sampled columns C5")
+    inp = synth.make_inputs(cfg)
+    fs = synth.init_factors(cfg)
+    ctx = lib.Context(cfg.o, cfg.v, cfg.nx, cfg.rank, "bf16")
+    ctx.load_t2(inp.t)
+    ctx.load_df(inp.b_vv)
+    ctx.set_factors(*fs)
+    cols = [0, 1023, cfg.rank - 1]
+    sub = [f[:, cols] for f in fs]
+    for mode in (0, 2):
+        got = ctx.mttkrp(mode)[:, cols]
+        want = oracle.mttkrp_chain(inp.t, inp.b_vv, sub, mode)
+        err = assert_lowp(got, want, abs_chain(inp.t, inp.b_vv, sub, mode), N_ROUND_BF16,
+                          chain_lengths(cfg.o, cfg.v, cfg.nx, mode), f"C5 mode {mode}")
+        _say(f"  mode {mode}: rel err {err:.2e}")
+    ctx.close()
