@@ -269,6 +269,47 @@ def test_gemm_bf16_chained_bitwise(env, which):
     assert torch.equal(whole.view(torch.int16), cut.view(torch.int16))
 
 
+@pytest.mark.parametrize("which", ["Y", "Z"])
+def test_gemm_bf16_b_resident_full_size(env, which):
+    """The C3 shapes of Y = F^T B (1024 x 196608, K = 256) and Z = Y tau per r
+    (1024 batches of 768 x 256, K = 256) on the B-resident kernel, with its
+    register ring and padded trips exactly as the sweep launches them: bit for
+    bit against the tiled kernel (reached through a C row stride that is not a
+    multiple of 8), and sampled columns against float64 products."""
+    L, torch = env
+    v, X, R = 256, 768, 1024
+    _say(f"gemm bf16 B resident full size {which}")
+    g = torch.Generator(device="cuda").manual_seed(11)
+    stream = torch.cuda.current_stream().cuda_stream
+    if which == "Y":
+        M, N, K, batch = R, X * v, v, 1
+    else:
+        M, N, K, batch = X, v, v, R
+    a = torch.randn(batch * M * K, device="cuda", generator=g).to(torch.bfloat16)
+    b = torch.randn(batch * N * K, device="cuda", generator=g).to(torch.bfloat16)
+    out = {}
+    for scm in (N, N + 4):
+        c = torch.full((batch * M * scm,), 7.0, dtype=torch.bfloat16, device="cuda")
+        st = L.cpppl_test_gemm(1, M, N, K, batch, a.data_ptr(), K, 1, M * K, b.data_ptr(), 1, K,
+                               N * K, c.data_ptr(), scm, M * scm, 2, 1.0, 0.0, 1, 0, stream)
+        assert st == 0
+        full = c.view(batch, M, scm)
+        if scm > N:
+            assert torch.all(full[:, :, N:].float() == 7.0)
+        out[scm] = full[:, :, :N].contiguous()
+        del c, full
+    torch.cuda.synchronize()
+    assert torch.equal(out[N].view(torch.int16), out[N + 4].view(torch.int16))
+    a3 = a.view(batch, M, K).double()
+    b3 = b.view(batch, N, K).double()
+    for bi in sorted({0, batch // 2, batch - 1}):
+        for col in sorted({0, N // 3, N - 1}):
+            want = (a3[bi] @ b3[bi, col]).cpu().numpy()
+            got = out[N][bi, :, col].double().cpu().numpy()
+            err = np.abs(got - want).max() / np.abs(want).max()
+            assert err <= 8e-3, (which, bi, col, err)
+
+
 @pytest.mark.parametrize("R,n", [(1, 3), (17, 5), (64, 64), (65, 7), (300, 130), (1024, 256),
                                  (2048, 32)])
 def test_spd_inverse_solve(env, R, n):
