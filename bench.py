@@ -86,11 +86,11 @@ def traffic_for(kernel):
 
 
 # BF16 products of one ALS sweep in issue order (main stream).  While a
-# side-stream inverse is pending the library cuts tau and G into four launches
-# and Z into two (Y and the split-K products stay whole), so a class call is
+# side-stream inverse is pending the library cuts tau into four launches and
+# Z and G into two (Y and the split-K products stay whole), so a class call is
 # LAUNCHES[cls] consecutive BF16 GEMM dispatches (kernels named gemm_bf16*).
 SWEEP_GEMMS = ["kr_t2", "z", "m", "y", "z", "m", "y", "g", "h"]
-LAUNCHES = {"kr_t2": 4, "y": 1, "z": 2, "g": 4, "m": 1, "h": 1}
+LAUNCHES = {"kr_t2": 4, "y": 1, "z": 2, "g": 2, "m": 1, "h": 1}
 
 
 def digest_counters(fetch_csv, write_csv, steps, calib_mib, out_path):

@@ -323,8 +323,12 @@ int splits_for(cpppl_ctx* c, const Path& P, int64_t M, int64_t N, int64_t K, int
 // alternating on one box, 391 sweeps/s with Y whole and Z in two launches,
 // 390 with Z whole, 385 with Z in four (Y in four: 6 % slower than whole).
 constexpr int Y_LAUNCHES = 1, Z_LAUNCHES = 2;
-// tau and G (tiled kernel) keep four.
-constexpr int TAU_LAUNCHES = 4, G_LAUNCHES = 4;
+// tau keeps four launches (one measured the same sweep rate).  G, 1024 batches
+// of 256 x 256 from K = X, in two launches of two rounds of work-groups each:
+// 396.5 sweeps/s on average against 394.1 with four one-round launches and
+// 390.4 with one launch (three alternating runs each), G 230 against 265 us
+// per call.
+constexpr int TAU_LAUNCHES = 4, G_LAUNCHES = 2;
 
 // tau[r][cd] = sum_ij Kt[r][ij] t[ij][cd], Kt = KR(gamma, rho)   (path dtype)
 void compute_tau(cpppl_ctx* c, const Path& P) {
